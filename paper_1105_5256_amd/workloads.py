@@ -1,0 +1,119 @@
+"""Seeded synthetic inputs for the lattice GMRF workloads.
+
+This module only draws and lays out input data (lattice shapes, kappa^2
+values and fields, observation points with their bilinear weights, greedy
+priorities).  It holds none of the log-determinant method's arithmetic and is
+the single source of inputs for both the library's tests/benchmark and the
+CPU reference, so that both see identical arrays.  Random numbers come from
+numpy's PCG64 (``numpy.random.default_rng(seed)``).
+
+The paper's experiments (Sec. 3) use simulated SPDE fields on 2-D lattices of
+unstated size and a 3-D lattice with about two million sites; these inputs
+are synthetic stand-ins with the same operators and scales:
+
+* ``lattice2d_5pt``   Q = kappa2 I + L, 5-point Dirichlet Laplacian;
+* ``lattice2d_sq``    Q = (kappa2 I + L)^2, the 13-point operator;
+* ``lattice3d_field`` Q = diag(kappa2(s)) + L (7-point) with
+                      log kappa2(s) = eta0 + eta1 z(s), z a smooth standardised
+                      Gaussian field;
+* ``posterior2d``     Q_p = (kappa2 I + L)^2 + tau A^T A with A the bilinear
+                      interpolation at uniformly scattered points;
+* ``batch2d``         many independent square fields of uneven size and
+                      kappa2 ~ LogUniform(0.01, 1).
+"""
+import numpy as np
+
+
+def lattice2d_5pt(m=64, kappa2=0.1, k=2):
+    """Plain 2-D SPDE precision kappa2 I + L on an m x m lattice."""
+    return dict(kind="5pt", shape=(m, m), kappa2=float(kappa2), power=1, k=int(k))
+
+
+def lattice2d_sq(mx=512, my=None, kappa2=0.05, k=4):
+    """Squared operator (kappa2 I + L)^2 on an mx x my lattice."""
+    my = mx if my is None else my
+    return dict(kind="sq", shape=(mx, my), kappa2=float(kappa2), power=2, k=int(k))
+
+
+def smooth_field(shape, sigma, seed):
+    """Standardised smooth Gaussian field: white noise N(0, 1) on the lattice,
+    convolved periodically (FFT) with a Gaussian kernel of standard deviation
+    ``sigma`` sites, then shifted/scaled to sample mean 0 and sd 1.
+    Returned flat in site order (x fastest)."""
+    rshape = tuple(reversed(tuple(int(m) for m in shape)))
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(rshape)
+    freqs = np.meshgrid(*[np.fft.fftfreq(m) for m in rshape], indexing="ij")
+    f2 = sum(f * f for f in freqs)
+    kernel_hat = np.exp(-2.0 * np.pi ** 2 * sigma ** 2 * f2)
+    z = np.real(np.fft.ifftn(np.fft.fftn(w) * kernel_hat))
+    z = (z - z.mean()) / z.std()
+    return z.ravel()
+
+
+def lattice3d_field(m=128, eta=(np.log(0.1), 0.5), sigma=8.0, seed=3, k=2, shape=None):
+    """3-D precision diag(kappa2(s)) + L with log kappa2 = eta0 + eta1 z(s).
+
+    Returns the field z and the inputs derived from it: kappa2 (the operator's
+    diagonal shift) and the two derivative diagonals d kappa2 / d eta0 = kappa2,
+    d kappa2 / d eta1 = kappa2 * z (the operator is linear in kappa2)."""
+    shape = (m, m, m) if shape is None else tuple(shape)
+    z = smooth_field(shape, sigma, seed)
+    kappa2 = np.exp(eta[0] + eta[1] * z)
+    return dict(kind="3d", shape=shape, eta=tuple(float(e) for e in eta), z=z,
+                kappa2_field=kappa2, dkappa2=[kappa2, kappa2 * z], power=1, k=int(k))
+
+
+def observations(shape, nobs, seed):
+    """Uniform points in [0, mx - 1) x [0, my - 1) with bilinear weights.
+
+    Returns (corner (nobs x 4 int32 site ids), weight (nobs x 4 float64)) for
+    the corners (x0, y0), (x0 + 1, y0), (x0, y0 + 1), (x0 + 1, y0 + 1) of the
+    cell holding each point."""
+    mx, my = shape
+    rng = np.random.default_rng(seed)
+    px = rng.uniform(0.0, mx - 1.0, nobs)
+    py = rng.uniform(0.0, my - 1.0, nobs)
+    ix = np.minimum(np.floor(px).astype(np.int64), mx - 2)
+    iy = np.minimum(np.floor(py).astype(np.int64), my - 2)
+    fx = px - ix
+    fy = py - iy
+    s00 = ix + mx * iy
+    corner = np.stack([s00, s00 + 1, s00 + mx, s00 + mx + 1], axis=1).astype(np.int32)
+    weight = np.stack([(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy], axis=1)
+    return corner, weight
+
+
+def posterior2d(m=1024, kappa2=0.05, tau=100.0, nobs=100_000, seed=4, k=4, shape=None):
+    """Gauss-linear posterior precision (kappa2 I + L)^2 + tau A^T A."""
+    shape = (m, m) if shape is None else tuple(shape)
+    corner, weight = observations(shape, nobs, seed)
+    return dict(kind="post", shape=shape, kappa2=float(kappa2), power=2, tau=float(tau),
+                corner=corner, weight=weight, k=int(k))
+
+
+def batch2d(nfields=256, side_lo=32, side_hi=256, seed=5, k=4):
+    """Independent fields (kappa2_f I + L)^2 on side_f x side_f lattices with
+    side_f ~ U{side_lo..side_hi} and kappa2_f ~ LogUniform(0.01, 1)."""
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(side_lo, side_hi + 1, nfields)
+    kappa2 = np.exp(rng.uniform(np.log(0.01), np.log(1.0), nfields))
+    fields = [dict(kind="sq", shape=(int(s), int(s)), kappa2=float(c), power=2, k=int(k))
+              for s, c in zip(sides, kappa2)]
+    return dict(kind="batch", fields=fields)
+
+
+def priority(n, seed):
+    """A seeded random permutation of 0..n-1, used as greedy colouring priority."""
+    return np.random.default_rng(seed).permutation(n).astype(np.int32)
+
+
+# Full-size workloads of the benchmark configurations.
+def full_configs():
+    return {
+        "lattice64_5pt": lattice2d_5pt(64, 0.1, k=2),
+        "lattice512_sq": lattice2d_sq(512, kappa2=0.05, k=4),
+        "lattice128c_field": lattice3d_field(128, k=2),
+        "posterior1024": posterior2d(1024),
+        "batch256": batch2d(256),
+    }
