@@ -1,0 +1,213 @@
+/*
+ * ldq.h -- C ABI of the MI355X (gfx950) probing / multi-shift Krylov
+ * log-determinant library.
+ *
+ * Method (Aune & Simpson, "Parameter Estimation in High Dimensional Gaussian
+ * Distributions", arXiv 1105.5256):
+ *   * log det Q = tr log Q (Sec. 2.1, eq. (5));
+ *   * tr log Q ~ sum_j v_j^T log(Q) v_j with probing vectors v_j, the 0/1
+ *     indicators of the colour classes of a distance-k colouring of the graph
+ *     of Q (Sec. 2.1, probing paragraph);
+ *   * log(Q) v_j ~ sum_l c_l (Q - sigma_l I)^{-1} v_j, a contour-quadrature
+ *     rational approximation that needs an enclosure [lambda_min, lambda_max]
+ *     of the spectrum (Sec. 2.1, eq. (7));
+ *   * all shifted systems of one probe are solved by one conjugate-gradient
+ *     recurrence with per-shift scalar coefficients (CG-M / COCG-M, Sec. 2.1,
+ *     last paragraph).
+ * The gradient d log det Q / d eta = tr(Q^{-1} dQ/d eta) needed by the
+ * hyperparameter optimisation of Sec. 1 (eq. (4)) and Sec. 3 is estimated by
+ * probing as sum_j x_j^T (dQ/d eta) v_j with x_j = Q^{-1} v_j from the same
+ * Krylov run (the paper gives no gradient; this is the library's reading).
+ *
+ * Conventions (every entry point):
+ *   * Every call returns an ldq_status; nothing is thrown across the ABI and
+ *     the process is never terminated.  On failure ldq_last_error() holds a
+ *     human-readable detail (thread-local, valid until the next call on the
+ *     same thread).
+ *   * Output arguments are written only on LDQ_OK, except that
+ *     LDQ_E_NO_CONVERGENCE still writes the current estimate and the info.
+ *   * Pointers are host pointers unless an argument says otherwise or
+ *     LDQ_FLAG_DEVICE_PTR is passed.  Host inputs are copied before the call
+ *     returns; the caller keeps ownership.  Device inputs (flag set) are
+ *     borrowed and must stay valid until the object that borrows them is
+ *     destroyed.  The context owns every device allocation it makes.
+ *   * Work is enqueued on the context's HIP stream; calls that return scalars
+ *     block until those scalars are on the host.
+ *   * A context must not be used by two threads at the same time.
+ *   * Lattice sites are numbered s = x + nx * (y + ny * z) (x fastest).
+ */
+#ifndef LDQ_H
+#define LDQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LDQ_OK = 0,
+  LDQ_E_INVALID = 1,         /* an argument is out of range or inconsistent */
+  LDQ_E_NOT_SPD = 2,         /* the Krylov run met p^T Q p <= 0 or a non-finite value */
+  LDQ_E_NO_CONVERGENCE = 3,  /* max_iter reached; current estimate and info are written */
+  LDQ_E_ENCLOSURE = 4,       /* the spectrum enclosure is invalid (lambda_min <= 0, ...) */
+  LDQ_E_DEVICE = 5,          /* a HIP runtime call failed */
+  LDQ_E_NO_MEMORY = 6,       /* a device or host allocation failed */
+  LDQ_E_UNSUPPORTED = 7      /* a valid request this library does not implement */
+} ldq_status;
+
+/* Name of a status code (static string). */
+const char *ldq_status_string(int status);
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *ldq_last_error(void);
+
+/* ---------------------------------------------------------------- context */
+
+typedef struct ldq_ctx ldq_ctx;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the handle. */
+int ldq_create(int device, void *hip_stream, ldq_ctx **out);
+/* Release the context and all device memory it owns (NULL is ignored).
+ * Operators created on it must be destroyed first. */
+void ldq_destroy(ldq_ctx *ctx);
+/* Change the stream later calls enqueue on (NULL = default stream). */
+int ldq_set_stream(ldq_ctx *ctx, void *hip_stream);
+
+/* -------------------------------------------------------------- operators */
+
+typedef struct ldq_op ldq_op;
+
+/* Lattice operator kinds (Sec. 3: the SPDE precision on a regular lattice). */
+enum {
+  LDQ_SHIFTED_LAPLACIAN = 1,         /* M = diag(kappa2) + L: 5-point (2-D) or 7-point (3-D) */
+  LDQ_SQUARED_SHIFTED_LAPLACIAN = 2  /* M @ M with constant kappa2: the 13-point 2-D operator */
+};
+enum { LDQ_FLAG_DEVICE_PTR = 1 };    /* array arguments are device pointers (borrowed) */
+
+/* scale * (kappa2 I + L)^p on an ndim-dimensional box shape[0..ndim-1]
+ * (ndim = 2 or 3; every extent >= 1) with Dirichlet boundary: values outside
+ * the box are zero, so boundary rows keep the full diagonal.
+ *   kind          LDQ_SHIFTED_LAPLACIAN or LDQ_SQUARED_SHIFTED_LAPLACIAN (ndim = 2 only)
+ *   kappa2        constant shift (used when kappa2_field is NULL)
+ *   kappa2_field  NULL, or n = prod(shape) per-site values of kappa2 (SHIFTED only)
+ *   scale         factor applied to the whole operator (e.g. 2 for dQ/dkappa2 = 2M)
+ *   flags         0 or LDQ_FLAG_DEVICE_PTR (then kappa2_field is a device pointer) */
+int ldq_op_lattice(ldq_ctx *ctx, int ndim, const int64_t *shape, int kind, double kappa2,
+                   const double *kappa2_field, double scale, unsigned flags, ldq_op **out);
+
+/* General sparse symmetric operator in CSR form (n rows, nnz entries,
+ * rowptr[n + 1], colind[nnz] (int32, sorted within a row), val[nnz]).
+ * The pattern must be symmetric; the values are used as given. */
+int ldq_op_csr(ldq_ctx *ctx, int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colind,
+               const double *val, unsigned flags, ldq_op **out);
+
+/* Diagonal operator diag(d), d[n]. */
+int ldq_op_diag(ldq_ctx *ctx, int64_t n, const double *d, unsigned flags, ldq_op **out);
+
+/* Gauss-linear observation term (Sec. 1, eq. (1) and the posterior precision
+ * Q_p = Q_x + A^T Q_1 A with Q_1 = tau I).  A has nobs rows; row o has the
+ * four entries weight[4 o + c] in columns corner[4 o + c] (c = 0..3), which
+ * must be sites of one lattice cell: (x, y), (x+1, y), (x, y+1), (x+1, y+1).
+ * ldq_op_add_obs adds tau * A^T A to a 2-D lattice operator in place;
+ * ldq_op_obs_gram creates A^T A alone (for dQ_p / dtau) on the lattice of
+ * `like`.  corner and weight are host arrays. */
+int ldq_op_add_obs(ldq_op *Q, int64_t nobs, const int32_t *corner, const double *weight, double tau);
+int ldq_op_obs_gram(ldq_ctx *ctx, const ldq_op *like, int64_t nobs, const int32_t *corner,
+                    const double *weight, ldq_op **out);
+
+/* Number of rows of an operator. */
+int64_t ldq_op_size(const ldq_op *op);
+void ldq_op_destroy(ldq_op *op);
+
+/* --------------------------------------------------------------- options */
+
+enum { LDQ_FP64 = 0,    /* vectors stored in FP64 */
+       LDQ_MIXED = 1 }; /* vectors and operator fields stored in FP32; every product,
+                           update, dot and recurrence computed in FP64 */
+enum {
+  LDQ_COLOUR_AUTO = 0,     /* modular for lattice operators, greedy for CSR */
+  LDQ_COLOUR_MODULAR = 1,  /* (x + a y [+ b z]) mod C, smallest valid C (lattices only) */
+  LDQ_COLOUR_GREEDY = 2,   /* sequential greedy in priority order (bit-exact on the device) */
+  LDQ_COLOUR_USER = 3,     /* user_colours[n] */
+  LDQ_COLOUR_IDENTITY = 4  /* every site its own class (n probes; exact up to quadrature) */
+};
+
+typedef struct {
+  int k;                        /* colouring distance in the graph of Q (>= 1) */
+  int colouring;                /* LDQ_COLOUR_* */
+  const int32_t *user_colours;  /* host, n entries in [0, C), for LDQ_COLOUR_USER */
+  const int32_t *priority;      /* host, n entries or NULL (= natural order): greedy visits
+                                   vertices by ascending priority, ties by index */
+  int nshifts;                  /* number of complex shifts N (1..64) */
+  double tol;                   /* shifted system l stops when |zeta_l| ||r|| / ||v|| <= tol */
+  double grad_tol;              /* with a gradient the base system runs until ||r|| / ||v|| <= grad_tol
+                                   (0 => tol) */
+  int max_iter;                 /* Krylov iteration cap per probe */
+  int precision;                /* LDQ_FP64 or LDQ_MIXED */
+  double lambda_min, lambda_max;/* spectrum enclosure; 0 => computed by the library */
+  int probe_block;              /* probes advanced together (0 = all) */
+  int check_every;              /* passes between convergence polls (0 = library default) */
+} ldq_options;
+
+/* Defaults: k = 2, AUTO colouring, N = 20, tol = 1e-10 (FP64) / 1e-5 (MIXED),
+ * grad_tol = 0, max_iter = 100000, FP64, enclosure computed, all probes. */
+void ldq_options_default(ldq_options *o);
+
+typedef struct {
+  int32_t ncolours;          /* non-empty colour classes = probes */
+  int32_t iters_max;         /* Krylov iterations of the slowest probe */
+  int64_t iters_total;       /* sum of iterations over probes */
+  double lambda_min, lambda_max;  /* enclosure used */
+  double max_rel_residual;   /* max over probes of the final ||r|| / ||v|| */
+  double seconds;            /* host wall time of the call */
+  double loop_seconds;       /* device time of the Krylov passes (HIP events on the ctx stream) */
+  int64_t passes;            /* pass-kernel launches */
+  int64_t probe_passes;      /* sum over launches of the probes each launch advanced */
+  double bytes_model;        /* algorithmic bytes of those probe passes (see DESIGN) */
+} ldq_info;
+
+/* ------------------------------------------------------------- the method */
+
+/* a1: the colouring that defines the probes (Sec. 2.1, probing paragraph).
+ * method = LDQ_COLOUR_MODULAR / GREEDY / IDENTITY; priority as in ldq_options.
+ * colours: host int32[n] output; *ncolours receives C (max colour + 1). */
+int ldq_colouring(ldq_ctx *ctx, const ldq_op *Q, int k, int method, const int32_t *priority,
+                  int32_t *colours, int32_t *ncolours);
+
+/* a2: enclosure [lambda_min, lambda_max] of the spectrum of Q that the
+ * quadrature needs (Sec. 2.1, the paragraph before eq. (7)). */
+int ldq_spectrum_bounds(ldq_ctx *ctx, const ldq_op *Q, double *lambda_min, double *lambda_max);
+
+/* a3: shifts sigma_l and weights c_l (l = 1..N) with
+ * log(lambda) ~ Im sum_l c_l / (lambda - sigma_l) on [lambda_min, lambda_max]
+ * (eq. (7)).  sigma, coef: host double[2 N] as (re, im) pairs. */
+int ldq_shifts(ldq_ctx *ctx, double lambda_min, double lambda_max, int nshifts,
+               double *sigma, double *coef);
+
+/* a4-a6: log det Q ~ sum_j Im sum_l c_l v_j^T (Q - sigma_l I)^{-1} v_j. */
+int ldq_logdet(ldq_ctx *ctx, const ldq_op *Q, const ldq_options *opts, double *logdet,
+               ldq_info *info /* nullable */);
+
+/* a4-a7: log det Q and grad[i] ~ sum_j x_j^T dQ[i] v_j, x_j = Q^{-1} v_j,
+ * for nparams (0..4) derivative operators dQ[i] on the same lattice:
+ * LDQ_SHIFTED_LAPLACIAN (any scale/kappa2), diagonal, or observation gram. */
+int ldq_logdet_grad(ldq_ctx *ctx, const ldq_op *Q, int nparams, const ldq_op *const *dQ,
+                    const ldq_options *opts, double *logdet, double *grad, ldq_info *info);
+
+/* Per-probe terms of the last ldq_logdet / ldq_logdet_grad call on ctx:
+ * out[j * (1 + nparams) + 0] = Im sum_l c_l psi_jl, out[j * (1 + nparams) + 1 + i]
+ * = x_j^T dQ[i] v_j, for the j-th non-empty colour class in increasing colour
+ * order.  capacity = length of out; *count receives the number of probes. */
+int ldq_probe_terms(ldq_ctx *ctx, double *out, int64_t capacity, int64_t *count, int *nparams);
+
+/* Many independent fields (e.g. one operator per field); per field f:
+ * logdet[f], grad[f * nparams + i] (dQ[f * nparams + i]), info[f] (nullable). */
+int ldq_logdet_batched(ldq_ctx *ctx, int nfields, const ldq_op *const *Q, int nparams,
+                       const ldq_op *const *dQ, const ldq_options *opts, double *logdet,
+                       double *grad, ldq_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDQ_H */

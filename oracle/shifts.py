@@ -1,4 +1,4 @@
-"""Contour-quadrature rational approximation of log (oracle; test infrastructure only).
+r"""Contour-quadrature rational approximation of log (oracle; test infrastructure only).
 
 Sec. 2.1, eq. (7): log(Q) v ~ f_N(Q) v = sum_{l=1}^N alpha_l (Q - sigma_l I)^{-1} v,
 obtained from Cauchy's integral log(Q) = (1 / 2 pi i) \oint log(z) (z I - Q)^{-1} dz

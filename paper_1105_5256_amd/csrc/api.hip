@@ -1,0 +1,1089 @@
+// Host side of libldq: the C ABI (include/ldq.h), operators, device workspace
+// and the driver that launches the Krylov passes until every probe converged.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ldq.h"
+#include "ldq_internal.h"
+
+namespace ldq {
+// launchers (pass2d.hip, pass3d.hip, misc.hip, colour.hip)
+template <typename T> hipError_t launch_pass2d(const Pass2D<T> &, bool, bool, hipStream_t);
+template <typename T> hipError_t launch_pass3d(const Pass3D<T> &, hipStream_t);
+void pass2d_tiles(int nx, int ny, int *tiles_x, int *ntiles);
+void pass3d_tiles(int nx, int ny, int nz, int zseg, int *tiles_x, int *tiles_y, int *nzseg, int *ntiles);
+hipError_t launch_init_probes(ProbeState *, int, const int32_t *, int *, hipStream_t);
+hipError_t launch_probe_terms(const ProbeState *, const ShiftState *, const cplx *, int, int, int, double *, int,
+                              int *, hipStream_t);
+hipError_t launch_sum_terms(const double *, int, int, double *, hipStream_t);
+hipError_t launch_shifts(double, double, int, cplx *, cplx *, hipStream_t);
+hipError_t launch_modular_fill(int32_t *, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_class_count(const int32_t *, size_t, int, int *, hipStream_t);
+hipError_t launch_colour_max(const int32_t *, size_t, int *, hipStream_t);
+hipError_t launch_minmax(const double *, size_t, double *, hipStream_t);
+hipError_t launch_csr_abs_rowsum(const int32_t *, const double *, int64_t, double *, hipStream_t);
+hipError_t launch_to_float(const double *, float *, size_t, hipStream_t);
+hipError_t launch_jp_round(const int32_t *, const int32_t *, int64_t, int, const int32_t *, int32_t *,
+                           unsigned long long *, unsigned long long *, int *, int *, hipStream_t);
+}  // namespace ldq
+
+using namespace ldq;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static int fail(int status, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+#define HIPCHK(expr)                                                                                \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) return fail(LDQ_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                      __FILE__, __LINE__);                                          \
+  } while (0)
+
+#define CHK(expr)            \
+  do {                       \
+    int s_ = (expr);         \
+    if (s_ != LDQ_OK) return s_; \
+  } while (0)
+
+extern "C" const char *ldq_status_string(int s) {
+  switch (s) {
+    case LDQ_OK: return "LDQ_OK";
+    case LDQ_E_INVALID: return "LDQ_E_INVALID";
+    case LDQ_E_NOT_SPD: return "LDQ_E_NOT_SPD";
+    case LDQ_E_NO_CONVERGENCE: return "LDQ_E_NO_CONVERGENCE";
+    case LDQ_E_ENCLOSURE: return "LDQ_E_ENCLOSURE";
+    case LDQ_E_DEVICE: return "LDQ_E_DEVICE";
+    case LDQ_E_NO_MEMORY: return "LDQ_E_NO_MEMORY";
+    case LDQ_E_UNSUPPORTED: return "LDQ_E_UNSUPPORTED";
+    default: return "LDQ_E_UNKNOWN";
+  }
+}
+
+extern "C" const char *ldq_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------- device buffers
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  int reserve(size_t want) {
+    if (want <= bytes) return LDQ_OK;
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+    size_t grow = std::max(want, (size_t)256);
+    if (hipMalloc(&ptr, grow) != hipSuccess) {
+      ptr = nullptr;
+      (void)hipGetLastError();
+      return fail(LDQ_E_NO_MEMORY, "hipMalloc of %zu bytes failed", grow);
+    }
+    bytes = grow;
+    return LDQ_OK;
+  }
+  void release() {
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T *as() const { return (T *)ptr; }
+};
+
+struct ldq_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  DevBuf vec, partials, counters, pstate, sstate, shifts, classes, terms, stats, sums, misc, colbuf, jpkey, jpmask;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<double> last_terms;
+  int last_nparams = 0;
+  int64_t last_count = 0;
+};
+
+enum OpKind { OPK_LATTICE = 1, OPK_CSR = 2, OPK_DIAG = 3, OPK_OBSGRAM = 4 };
+
+struct ldq_op {
+  ldq_ctx *ctx = nullptr;
+  int kind = 0;
+  int ndim = 0;
+  int64_t shape[3] = {1, 1, 1};
+  int64_t n = 0;
+  int lkind = 0;
+  double kappa2 = 0.0, scale = 1.0;
+  double k2min = 0.0, k2max = 0.0;
+  double *field = nullptr;     // kappa2 field (lattice) or d (diag), FP64 on device
+  bool own_field = false;
+  float *field32 = nullptr;
+  // observation term (2-D lattice, or the gram operator itself)
+  double tau = 0.0;
+  int64_t nobs = 0;
+  double *obs9 = nullptr;      // 9 x n planes, FP64
+  float *obs9_32 = nullptr;
+  double obs_gersh = 0.0;      // max row sum of |A^T A|
+  // CSR
+  int64_t nnz = 0;
+  int32_t *rowptr = nullptr, *colind = nullptr;
+  double *val = nullptr;
+  bool own_csr = false;
+};
+
+static int set_device(ldq_ctx *ctx) {
+  HIPCHK(hipSetDevice(ctx->device));
+  return LDQ_OK;
+}
+
+// ---------------------------------------------------------------- context
+extern "C" int ldq_create(int device, void *hip_stream, ldq_ctx **out) {
+  if (!out) return fail(LDQ_E_INVALID, "out is NULL");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    return fail(LDQ_E_DEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= ndev) return fail(LDQ_E_INVALID, "device %d out of range (%d devices)", device, ndev);
+  ldq_ctx *c = new (std::nothrow) ldq_ctx();
+  if (!c) return fail(LDQ_E_NO_MEMORY, "context allocation failed");
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
+      hipEventCreate(&c->ev1) != hipSuccess) {
+    delete c;
+    return fail(LDQ_E_DEVICE, "hipSetDevice/hipEventCreate failed");
+  }
+  *out = c;
+  return LDQ_OK;
+}
+
+extern "C" void ldq_destroy(ldq_ctx *c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (DevBuf *b : {&c->vec, &c->partials, &c->counters, &c->pstate, &c->sstate, &c->shifts, &c->classes,
+                    &c->terms, &c->stats, &c->sums, &c->misc, &c->colbuf, &c->jpkey, &c->jpmask})
+    b->release();
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  delete c;
+}
+
+extern "C" int ldq_set_stream(ldq_ctx *c, void *hip_stream) {
+  if (!c) return fail(LDQ_E_INVALID, "ctx is NULL");
+  c->stream = (hipStream_t)hip_stream;
+  return LDQ_OK;
+}
+
+// -------------------------------------------------------------- operators
+static int upload(ldq_ctx *c, const void *src, size_t bytes, unsigned flags, void **dst, bool *own) {
+  if (flags & LDQ_FLAG_DEVICE_PTR) {
+    *dst = (void *)src;
+    *own = false;
+    return LDQ_OK;
+  }
+  if (hipMalloc(dst, std::max<size_t>(bytes, 4)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LDQ_E_NO_MEMORY, "hipMalloc of %zu bytes failed", bytes);
+  }
+  *own = true;
+  HIPCHK(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LDQ_OK;
+}
+
+// min and max of a device FP64 array (deterministic)
+static int device_minmax(ldq_ctx *c, const double *v, size_t n, double *lo, double *hi) {
+  CHK(c->misc.reserve(512 * sizeof(double)));
+  HIPCHK(launch_minmax(v, n, c->misc.as<double>(), c->stream));
+  std::vector<double> h(512);
+  HIPCHK(hipMemcpyAsync(h.data(), c->misc.ptr, 512 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *lo = INFINITY;
+  *hi = -INFINITY;
+  for (int b = 0; b < 256; ++b) {
+    *lo = std::min(*lo, h[2 * b]);
+    *hi = std::max(*hi, h[2 * b + 1]);
+  }
+  return LDQ_OK;
+}
+
+extern "C" int ldq_op_lattice(ldq_ctx *c, int ndim, const int64_t *shape, int kind, double kappa2,
+                              const double *kappa2_field, double scale, unsigned flags, ldq_op **out) {
+  if (!c || !shape || !out) return fail(LDQ_E_INVALID, "NULL argument");
+  if (ndim != 2 && ndim != 3) return fail(LDQ_E_INVALID, "ndim must be 2 or 3 (got %d)", ndim);
+  if (kind != LDQ_SHIFTED_LAPLACIAN && kind != LDQ_SQUARED_SHIFTED_LAPLACIAN)
+    return fail(LDQ_E_INVALID, "unknown lattice kind %d", kind);
+  if (kind == LDQ_SQUARED_SHIFTED_LAPLACIAN && (ndim != 2 || kappa2_field))
+    return fail(LDQ_E_UNSUPPORTED, "the squared operator is implemented for 2-D lattices with a constant kappa2");
+  if (!std::isfinite(kappa2) || !std::isfinite(scale) || scale <= 0.0)
+    return fail(LDQ_E_INVALID, "kappa2 and scale must be finite, scale > 0");
+  int64_t n = 1;
+  for (int d = 0; d < ndim; ++d) {
+    if (shape[d] < 1 || shape[d] > (1 << 20)) return fail(LDQ_E_INVALID, "shape[%d] = %lld out of range", d,
+                                                           (long long)shape[d]);
+    n *= shape[d];
+  }
+  if (n > (int64_t)1 << 30) return fail(LDQ_E_INVALID, "lattice too large (%lld sites)", (long long)n);
+  CHK(set_device(c));
+  ldq_op *op = new ldq_op();
+  op->ctx = c;
+  op->kind = OPK_LATTICE;
+  op->ndim = ndim;
+  for (int d = 0; d < ndim; ++d) op->shape[d] = shape[d];
+  op->n = n;
+  op->lkind = kind;
+  op->kappa2 = kappa2;
+  op->scale = scale;
+  op->k2min = op->k2max = kappa2;
+  if (kappa2_field) {
+    int st = upload(c, kappa2_field, n * sizeof(double), flags, (void **)&op->field, &op->own_field);
+    if (st == LDQ_OK) st = device_minmax(c, op->field, n, &op->k2min, &op->k2max);
+    if (st != LDQ_OK) {
+      ldq_op_destroy(op);
+      return st;
+    }
+    if (!std::isfinite(op->k2min) || !std::isfinite(op->k2max)) {
+      ldq_op_destroy(op);
+      return fail(LDQ_E_INVALID, "kappa2_field has non-finite values");
+    }
+  }
+  *out = op;
+  return LDQ_OK;
+}
+
+extern "C" int ldq_op_diag(ldq_ctx *c, int64_t n, const double *d, unsigned flags, ldq_op **out) {
+  if (!c || !d || !out || n < 1) return fail(LDQ_E_INVALID, "invalid diagonal operator arguments");
+  CHK(set_device(c));
+  ldq_op *op = new ldq_op();
+  op->ctx = c;
+  op->kind = OPK_DIAG;
+  op->n = n;
+  int st = upload(c, d, n * sizeof(double), flags, (void **)&op->field, &op->own_field);
+  if (st != LDQ_OK) {
+    ldq_op_destroy(op);
+    return st;
+  }
+  *out = op;
+  return LDQ_OK;
+}
+
+extern "C" int ldq_op_csr(ldq_ctx *c, int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colind,
+                          const double *val, unsigned flags, ldq_op **out) {
+  if (!c || !rowptr || !colind || !val || !out || n < 1 || nnz < 0 || nnz >= ((int64_t)1 << 31))
+    return fail(LDQ_E_INVALID, "invalid CSR arguments");
+  if (!(flags & LDQ_FLAG_DEVICE_PTR)) {
+    if (rowptr[0] != 0 || rowptr[n] != nnz) return fail(LDQ_E_INVALID, "rowptr[0] must be 0 and rowptr[n] = nnz");
+    for (int64_t i = 0; i < n; ++i) {
+      if (rowptr[i + 1] < rowptr[i]) return fail(LDQ_E_INVALID, "rowptr not monotone at row %lld", (long long)i);
+      for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        if (colind[e] < 0 || colind[e] >= n)
+          return fail(LDQ_E_INVALID, "colind[%d] = %d out of range", e, colind[e]);
+        if (e > rowptr[i] && colind[e] <= colind[e - 1])
+          return fail(LDQ_E_INVALID, "colind not strictly increasing in row %lld", (long long)i);
+      }
+    }
+  }
+  CHK(set_device(c));
+  ldq_op *op = new ldq_op();
+  op->ctx = c;
+  op->kind = OPK_CSR;
+  op->n = n;
+  op->nnz = nnz;
+  bool o1, o2, o3;
+  int st = upload(c, rowptr, (n + 1) * sizeof(int32_t), flags, (void **)&op->rowptr, &o1);
+  if (st == LDQ_OK) st = upload(c, colind, nnz * sizeof(int32_t), flags, (void **)&op->colind, &o2);
+  if (st == LDQ_OK) st = upload(c, val, nnz * sizeof(double), flags, (void **)&op->val, &o3);
+  op->own_csr = !(flags & LDQ_FLAG_DEVICE_PTR);
+  if (st != LDQ_OK) {
+    ldq_op_destroy(op);
+    return st;
+  }
+  *out = op;
+  return LDQ_OK;
+}
+
+// A^T A as 9 coefficient planes: plane d = (dy + 1) * 3 + (dx + 1) holds the
+// entry between site s and s + dx + nx dy.  Accumulated on the host in
+// observation order (deterministic), once per operator.
+static int build_obs_planes(ldq_op *op, int64_t nobs, const int32_t *corner, const double *weight,
+                            std::vector<double> &planes) {
+  const int64_t nx = op->shape[0], ny = op->shape[1], n = op->n;
+  planes.assign(9 * (size_t)n, 0.0);
+  for (int64_t o = 0; o < nobs; ++o) {
+    const int32_t *cs = corner + 4 * o;
+    const double *ws = weight + 4 * o;
+    if (!std::isfinite(ws[0]) || !std::isfinite(ws[1]) || !std::isfinite(ws[2]) || !std::isfinite(ws[3]))
+      return fail(LDQ_E_INVALID, "observation %lld has a non-finite weight", (long long)o);
+    const int32_t s00 = cs[0];
+    if (s00 < 0 || s00 >= n) return fail(LDQ_E_INVALID, "observation %lld: corner out of range", (long long)o);
+    const int64_t x0 = s00 % nx, y0 = s00 / nx;
+    if (x0 + 1 >= nx || y0 + 1 >= ny || cs[1] != s00 + 1 || cs[2] != s00 + nx || cs[3] != s00 + nx + 1)
+      return fail(LDQ_E_INVALID, "observation %lld: corners are not one lattice cell", (long long)o);
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        const int64_t sa = cs[a], sb = cs[b];
+        const int dx = (int)((sb % nx) - (sa % nx)), dy = (int)((sb / nx) - (sa / nx));
+        planes[(size_t)((dy + 1) * 3 + (dx + 1)) * n + sa] += ws[a] * ws[b];
+      }
+  }
+  double g = 0.0;
+  for (int64_t s = 0; s < n; ++s) {
+    double r = 0.0;
+    for (int d = 0; d < 9; ++d) r += std::fabs(planes[(size_t)d * n + s]);
+    g = std::max(g, r);
+  }
+  op->obs_gersh = g;
+  return LDQ_OK;
+}
+
+static int set_obs(ldq_op *op, int64_t nobs, const int32_t *corner, const double *weight) {
+  std::vector<double> planes;
+  CHK(build_obs_planes(op, nobs, corner, weight, planes));
+  if (op->obs9) hipFree(op->obs9);
+  if (op->obs9_32) hipFree(op->obs9_32);
+  op->obs9 = nullptr;
+  op->obs9_32 = nullptr;
+  bool own;
+  CHK(upload(op->ctx, planes.data(), planes.size() * sizeof(double), 0, (void **)&op->obs9, &own));
+  op->nobs = nobs;
+  return LDQ_OK;
+}
+
+extern "C" int ldq_op_add_obs(ldq_op *Q, int64_t nobs, const int32_t *corner, const double *weight, double tau) {
+  if (!Q || nobs < 0 || (nobs > 0 && (!corner || !weight)) || !(tau >= 0.0) || !std::isfinite(tau))
+    return fail(LDQ_E_INVALID, "invalid observation arguments");
+  if (Q->kind != OPK_LATTICE || Q->ndim != 2 || Q->lkind != LDQ_SQUARED_SHIFTED_LAPLACIAN)
+    return fail(LDQ_E_UNSUPPORTED, "observation terms are implemented for the 2-D squared operator");
+  CHK(set_device(Q->ctx));
+  CHK(set_obs(Q, nobs, corner, weight));
+  Q->tau = tau;
+  return LDQ_OK;
+}
+
+extern "C" int ldq_op_obs_gram(ldq_ctx *c, const ldq_op *like, int64_t nobs, const int32_t *corner,
+                               const double *weight, ldq_op **out) {
+  if (!c || !like || !out || nobs < 0 || (nobs > 0 && (!corner || !weight)))
+    return fail(LDQ_E_INVALID, "invalid observation arguments");
+  if (like->kind != OPK_LATTICE || like->ndim != 2) return fail(LDQ_E_UNSUPPORTED, "needs a 2-D lattice operator");
+  CHK(set_device(c));
+  ldq_op *op = new ldq_op();
+  op->ctx = c;
+  op->kind = OPK_OBSGRAM;
+  op->ndim = 2;
+  op->shape[0] = like->shape[0];
+  op->shape[1] = like->shape[1];
+  op->n = like->n;
+  op->tau = 1.0;
+  int st = set_obs(op, nobs, corner, weight);
+  if (st != LDQ_OK) {
+    ldq_op_destroy(op);
+    return st;
+  }
+  *out = op;
+  return LDQ_OK;
+}
+
+extern "C" int64_t ldq_op_size(const ldq_op *op) { return op ? op->n : 0; }
+
+extern "C" void ldq_op_destroy(ldq_op *op) {
+  if (!op) return;
+  if (op->ctx) {
+    hipSetDevice(op->ctx->device);
+    hipStreamSynchronize(op->ctx->stream);
+  }
+  if (op->own_field && op->field) hipFree(op->field);
+  if (op->field32) hipFree(op->field32);
+  if (op->obs9) hipFree(op->obs9);
+  if (op->obs9_32) hipFree(op->obs9_32);
+  if (op->own_csr) {
+    if (op->rowptr) hipFree(op->rowptr);
+    if (op->colind) hipFree(op->colind);
+    if (op->val) hipFree(op->val);
+  }
+  delete op;
+}
+
+// FP32 copies of operator data for LDQ_MIXED (made once, kept by the operator)
+static int field_as(ldq_op *op, const float **out) {
+  if (!op->field) {
+    *out = nullptr;
+    return LDQ_OK;
+  }
+  if (!op->field32) {
+    if (hipMalloc(&op->field32, op->n * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LDQ_E_NO_MEMORY, "FP32 field copy");
+    }
+    HIPCHK(launch_to_float(op->field, op->field32, op->n, op->ctx->stream));
+  }
+  *out = op->field32;
+  return LDQ_OK;
+}
+static int field_as(ldq_op *op, const double **out) {
+  *out = op->field;
+  return LDQ_OK;
+}
+static int obs_as(ldq_op *op, const float **out) {
+  if (!op->obs9) {
+    *out = nullptr;
+    return LDQ_OK;
+  }
+  if (!op->obs9_32) {
+    if (hipMalloc(&op->obs9_32, 9 * op->n * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LDQ_E_NO_MEMORY, "FP32 observation copy");
+    }
+    HIPCHK(launch_to_float(op->obs9, op->obs9_32, 9 * op->n, op->ctx->stream));
+  }
+  *out = op->obs9_32;
+  return LDQ_OK;
+}
+static int obs_as(ldq_op *op, const double **out) {
+  *out = op->obs9;
+  return LDQ_OK;
+}
+
+// ------------------------------------------------------------- options
+extern "C" void ldq_options_default(ldq_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->k = 2;
+  o->colouring = LDQ_COLOUR_AUTO;
+  o->nshifts = 20;
+  o->tol = 1e-10;
+  o->grad_tol = 0.0;
+  o->max_iter = 100000;
+  o->precision = LDQ_FP64;
+}
+
+// ------------------------------------------------------- a2: enclosure
+// Eigenvalues of the 1-D Dirichlet second difference of order m are
+// 4 sin^2(pi i / (2 (m + 1))); the lattice Laplacian adds one per axis.
+static void lap_extremes(const ldq_op *op, double *lo, double *hi) {
+  *lo = 0.0;
+  *hi = 0.0;
+  for (int d = 0; d < op->ndim; ++d) {
+    const double m = (double)op->shape[d];
+    const double a = std::sin(M_PI / (2.0 * (m + 1.0))), b = std::sin(M_PI * m / (2.0 * (m + 1.0)));
+    *lo += 4.0 * a * a;
+    *hi += 4.0 * b * b;
+  }
+}
+
+static int spectrum(const ldq_op *Q, double *lmin, double *lmax) {
+  if (Q->kind == OPK_LATTICE) {
+    double llo, lhi;
+    lap_extremes(Q, &llo, &lhi);
+    // Weyl: diag(kappa2) + L lies between (min kappa2) I + L and (max kappa2) I + L
+    double lo = Q->k2min + llo, hi = Q->k2max + lhi;
+    if (lo <= 0.0) return fail(LDQ_E_NOT_SPD, "lattice operator is not positive definite (lambda_min bound %g)", lo);
+    if (Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN) {
+      lo = lo * lo;
+      hi = hi * hi;
+    }
+    lo *= Q->scale;
+    hi *= Q->scale;
+    // A^T A is positive semidefinite with lambda_max <= its Gershgorin bound
+    if (Q->obs9) hi += Q->tau * Q->obs_gersh;
+    *lmin = lo;
+    *lmax = hi;
+    return LDQ_OK;
+  }
+  if (Q->kind == OPK_DIAG) {
+    ldq_ctx *c = Q->ctx;
+    CHK(device_minmax(c, Q->field, Q->n, lmin, lmax));
+    if (!(*lmin > 0.0)) return fail(LDQ_E_NOT_SPD, "diagonal operator has a non-positive entry");
+    return LDQ_OK;
+  }
+  return fail(LDQ_E_UNSUPPORTED, "no automatic enclosure for this operator kind; pass lambda_min/lambda_max");
+}
+
+extern "C" int ldq_spectrum_bounds(ldq_ctx *c, const ldq_op *Q, double *lmin, double *lmax) {
+  if (!c || !Q || !lmin || !lmax) return fail(LDQ_E_INVALID, "NULL argument");
+  CHK(set_device(c));
+  double lo, hi;
+  CHK(spectrum(Q, &lo, &hi));
+  *lmin = lo;
+  *lmax = hi;
+  return LDQ_OK;
+}
+
+// ------------------------------------------------------------ a3: shifts
+extern "C" int ldq_shifts(ldq_ctx *c, double lmin, double lmax, int N, double *sigma, double *coef) {
+  if (!c || !sigma || !coef) return fail(LDQ_E_INVALID, "NULL argument");
+  if (N < 1 || N > LDQ_MAXN) return fail(LDQ_E_INVALID, "nshifts must be in 1..%d", LDQ_MAXN);
+  if (!(lmin > 0.0) || !(lmax >= lmin) || !std::isfinite(lmax))
+    return fail(LDQ_E_ENCLOSURE, "invalid enclosure [%g, %g]", lmin, lmax);
+  CHK(set_device(c));
+  CHK(c->shifts.reserve(2 * LDQ_MAXN * sizeof(cplx)));
+  cplx *ds = c->shifts.as<cplx>(), *dc = ds + LDQ_MAXN;
+  HIPCHK(launch_shifts(lmin, lmax, N, ds, dc, c->stream));
+  HIPCHK(hipMemcpyAsync(sigma, ds, N * sizeof(cplx), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(coef, dc, N * sizeof(cplx), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LDQ_OK;
+}
+
+// ---------------------------------------------------------- a1: colouring
+struct Colouring {
+  int C = 0, a = 0, b = 0;          // modular parameters when C > 0 and colours == nullptr
+  const int32_t *colours = nullptr; // device array otherwise
+  int ncolours = 0;                 // C
+};
+
+// Smallest C (then smallest coefficients) with x + a y [+ b z] != 0 mod C for
+// every nonzero offset of L1 length <= D.  Lattice graph distance is the L1
+// distance for the 5/7-point operators and ceil(L1 / 2) for the 13-point one.
+static bool modular_ok(int dim, int D, int C, int a, int b) {
+  for (int dz = (dim == 3 ? -D : 0); dz <= (dim == 3 ? D : 0); ++dz)
+    for (int dy = -D; dy <= D; ++dy)
+      for (int dx = -D; dx <= D; ++dx) {
+        const int l1 = std::abs(dx) + std::abs(dy) + std::abs(dz);
+        if (l1 == 0 || l1 > D) continue;
+        long v = (long)dx + (long)a * dy + (long)b * dz;
+        if (((v % C) + C) % C == 0) return false;
+      }
+  return true;
+}
+
+static int modular_params(int dim, int D, int *C, int *a, int *b) {
+  for (int c = 1; c <= 4096; ++c) {
+    for (int x = 0; x < c; ++x)
+      for (int y = 0; y < (dim == 3 ? c : 1); ++y)
+        if (modular_ok(dim, D, c, x, y)) {
+          *C = c;
+          *a = x;
+          *b = y;
+          return LDQ_OK;
+        }
+  }
+  return fail(LDQ_E_UNSUPPORTED, "no modular colouring with at most 4096 colours for distance %d", D);
+}
+
+// CSR pattern of a lattice operator (host-built once for the greedy colouring).
+static void lattice_pattern(const ldq_op *op, std::vector<int32_t> &rp, std::vector<int32_t> &ci) {
+  const int64_t nx = op->shape[0], ny = op->shape[1], nz = op->ndim == 3 ? op->shape[2] : 1;
+  std::vector<int> off;
+  const bool sq = op->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN;
+  rp.assign(op->n + 1, 0);
+  ci.clear();
+  for (int64_t z = 0; z < nz; ++z)
+    for (int64_t y = 0; y < ny; ++y)
+      for (int64_t x = 0; x < nx; ++x) {
+        const int64_t s = (z * ny + y) * nx + x;
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx) {
+              const int l1 = std::abs(dx) + std::abs(dy) + std::abs(dz);
+              const bool in = sq ? (l1 >= 1 && l1 <= 2 && dz == 0) || (op->obs9 && std::abs(dx) <= 1 &&
+                                                                         std::abs(dy) <= 1 && l1 >= 1 && dz == 0)
+                                 : (l1 == 1 && (op->ndim == 3 || dz == 0));
+              if (!in) continue;
+              const int64_t xx = x + dx, yy = y + dy, zz = z + dz;
+              if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
+              ci.push_back((int32_t)((zz * ny + yy) * nx + xx));
+            }
+        rp[s + 1] = (int32_t)ci.size();
+      }
+}
+
+static int greedy_device(ldq_ctx *c, const ldq_op *Q, int k, const int32_t *prio_host, int32_t *dcol) {
+  const int64_t n = Q->n;
+  const int32_t *rp = nullptr, *ci = nullptr;
+  DevBuf tmp_rp, tmp_ci, tmp_prio;
+  std::vector<int32_t> hrp, hci;
+  if (Q->kind == OPK_CSR) {
+    rp = Q->rowptr;
+    ci = Q->colind;
+  } else if (Q->kind == OPK_LATTICE) {
+    lattice_pattern(Q, hrp, hci);
+    CHK(tmp_rp.reserve(hrp.size() * 4));
+    CHK(tmp_ci.reserve(std::max<size_t>(hci.size(), 1) * 4));
+    HIPCHK(hipMemcpyAsync(tmp_rp.ptr, hrp.data(), hrp.size() * 4, hipMemcpyHostToDevice, c->stream));
+    if (!hci.empty())
+      HIPCHK(hipMemcpyAsync(tmp_ci.ptr, hci.data(), hci.size() * 4, hipMemcpyHostToDevice, c->stream));
+    rp = tmp_rp.as<int32_t>();
+    ci = tmp_ci.as<int32_t>();
+  } else {
+    return fail(LDQ_E_UNSUPPORTED, "greedy colouring needs a lattice or CSR operator");
+  }
+  const int32_t *dprio = nullptr;
+  if (prio_host) {
+    for (int64_t i = 0; i < n; ++i)
+      if (prio_host[i] < 0) return fail(LDQ_E_INVALID, "priority values must be >= 0");
+    CHK(tmp_prio.reserve(n * 4));
+    HIPCHK(hipMemcpyAsync(tmp_prio.ptr, prio_host, n * 4, hipMemcpyHostToDevice, c->stream));
+    dprio = tmp_prio.as<int32_t>();
+  }
+  CHK(c->jpkey.reserve(2 * n * sizeof(unsigned long long)));
+  CHK(c->jpmask.reserve(2 * n * 4 * sizeof(unsigned long long)));
+  CHK(c->misc.reserve(4 * sizeof(int)));
+  HIPCHK(hipMemsetAsync(dcol, 0xff, n * sizeof(int32_t), c->stream));   // -1: uncoloured
+  int init[2] = {(int)n, 0};
+  HIPCHK(hipMemcpyAsync(c->misc.ptr, init, sizeof init, hipMemcpyHostToDevice, c->stream));
+  int h[2] = {(int)n, 0};
+  for (int64_t round = 0; h[0] > 0; ++round) {
+    if (round > n) return fail(LDQ_E_DEVICE, "greedy colouring made no progress");
+    for (int rr = 0; rr < 8; ++rr)
+      HIPCHK(launch_jp_round(rp, ci, n, k, dprio, dcol, c->jpkey.as<unsigned long long>(),
+                             c->jpmask.as<unsigned long long>(), c->misc.as<int>(), c->misc.as<int>() + 1,
+                             c->stream));
+    round += 7;
+    HIPCHK(hipMemcpyAsync(h, c->misc.ptr, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (h[1]) return fail(LDQ_E_UNSUPPORTED, "greedy colouring needs more than 256 colours");
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  tmp_rp.release();
+  tmp_ci.release();
+  tmp_prio.release();
+  return LDQ_OK;
+}
+
+static int lattice_radius(const ldq_op *Q, int k) {
+  return Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN ? 2 * k : k;
+}
+
+// Resolve the colouring of a call; array colourings are stored in ctx->colbuf.
+static int resolve_colouring(ldq_ctx *c, const ldq_op *Q, int k, int method, const int32_t *user,
+                             const int32_t *prio, Colouring *col) {
+  const int64_t n = Q->n;
+  if (method == LDQ_COLOUR_AUTO) method = (Q->kind == OPK_LATTICE) ? LDQ_COLOUR_MODULAR : LDQ_COLOUR_GREEDY;
+  if (method == LDQ_COLOUR_IDENTITY) {
+    if (Q->kind == OPK_LATTICE && n < ((int64_t)1 << 31)) {
+      // (x + nx y + nx ny z) mod n is the site index itself
+      col->C = (int)n;
+      col->a = (int)Q->shape[0];
+      col->b = (int)(Q->shape[0] * Q->shape[1]);
+      col->ncolours = (int)n;
+      return LDQ_OK;
+    }
+    std::vector<int32_t> iota(n);
+    for (int64_t i = 0; i < n; ++i) iota[i] = (int32_t)i;
+    CHK(c->colbuf.reserve(n * 4));
+    HIPCHK(hipMemcpyAsync(c->colbuf.ptr, iota.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    col->colours = c->colbuf.as<int32_t>();
+    col->ncolours = (int)n;
+    return LDQ_OK;
+  }
+  if (k < 1 && method != LDQ_COLOUR_USER) return fail(LDQ_E_INVALID, "colouring distance k must be >= 1");
+  if (method == LDQ_COLOUR_MODULAR) {
+    if (Q->kind != OPK_LATTICE) return fail(LDQ_E_UNSUPPORTED, "modular colouring needs a lattice operator");
+    CHK(modular_params(Q->ndim, lattice_radius(Q, k), &col->C, &col->a, &col->b));
+    col->ncolours = col->C;
+    return LDQ_OK;
+  }
+  CHK(c->colbuf.reserve(n * 4));
+  int32_t *dcol = c->colbuf.as<int32_t>();
+  if (method == LDQ_COLOUR_USER) {
+    if (!user) return fail(LDQ_E_INVALID, "user_colours is NULL");
+    HIPCHK(hipMemcpyAsync(dcol, user, n * 4, hipMemcpyHostToDevice, c->stream));
+  } else if (method == LDQ_COLOUR_GREEDY) {
+    CHK(greedy_device(c, Q, k, prio, dcol));
+  } else {
+    return fail(LDQ_E_INVALID, "unknown colouring method %d", method);
+  }
+  CHK(c->misc.reserve(4 * sizeof(int)));
+  int init[2] = {-1, 0};
+  HIPCHK(hipMemcpyAsync(c->misc.ptr, init, sizeof init, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_colour_max(dcol, n, c->misc.as<int>(), c->stream));
+  int h[2];
+  HIPCHK(hipMemcpyAsync(h, c->misc.ptr, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (h[1]) return fail(LDQ_E_INVALID, "negative colour value");
+  col->colours = dcol;
+  col->ncolours = h[0] + 1;
+  return LDQ_OK;
+}
+
+extern "C" int ldq_colouring(ldq_ctx *c, const ldq_op *Q, int k, int method, const int32_t *priority,
+                             int32_t *colours, int32_t *ncolours) {
+  if (!c || !Q || !colours || !ncolours) return fail(LDQ_E_INVALID, "NULL argument");
+  if (method == LDQ_COLOUR_USER || method == LDQ_COLOUR_AUTO) method = (Q->kind == OPK_LATTICE)
+                                                                          ? LDQ_COLOUR_MODULAR
+                                                                          : LDQ_COLOUR_GREEDY;
+  CHK(set_device(c));
+  Colouring col;
+  CHK(resolve_colouring(c, Q, k, method, nullptr, priority, &col));
+  const int64_t n = Q->n;
+  if (!col.colours) {
+    CHK(c->colbuf.reserve(n * 4));
+    HIPCHK(launch_modular_fill(c->colbuf.as<int32_t>(), (int)Q->shape[0], (int)Q->shape[1],
+                               Q->ndim == 3 ? (int)Q->shape[2] : 1, col.C, col.a, col.b, c->stream));
+    col.colours = c->colbuf.as<int32_t>();
+  }
+  HIPCHK(hipMemcpyAsync(colours, col.colours, n * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *ncolours = col.ncolours;
+  return LDQ_OK;
+}
+
+// --------------------------------------------------------- the Krylov driver
+struct Call {
+  ldq_ctx *c;
+  ldq_op *Q;
+  int nparams;
+  ldq_op *dQ[LDQ_MAXP];
+  ldq_options o;
+  Colouring col;
+  std::vector<int32_t> classes;   // non-empty colour classes (probe -> colour)
+  double lmin, lmax;
+  int ntiles;
+};
+
+template <typename T>
+static int fill_grad_terms(Call &k, GradTerm<T> *g) {
+  for (int i = 0; i < k.nparams; ++i) {
+    ldq_op *d = k.dQ[i];
+    GradTerm<T> t{};
+    if (d->kind == OPK_DIAG) {
+      t.kind = GK_DIAG;
+      t.scale = 1.0;
+      CHK(field_as(d, &t.field));
+    } else if (d->kind == OPK_LATTICE && d->lkind == LDQ_SHIFTED_LAPLACIAN) {
+      t.kind = GK_SHIFTED;
+      t.scale = d->scale;
+      t.kappa2 = d->kappa2;
+      CHK(field_as(d, &t.field));
+    } else if (d->kind == OPK_OBSGRAM) {
+      t.kind = GK_OBS;
+      t.scale = d->tau;
+      CHK(obs_as(d, &t.obs));
+    } else {
+      return fail(LDQ_E_UNSUPPORTED, "derivative operator %d: only shifted-Laplacian, diagonal and observation-gram"
+                  " operators are supported", i);
+    }
+    g[i] = t;
+  }
+  return LDQ_OK;
+}
+
+template <typename T>
+static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
+  ldq_ctx *c = k.c;
+  ldq_op *Q = k.Q;
+  const int64_t n = Q->n;
+  const int N = k.o.nshifts;
+  const int P = k.nparams;
+  const int nq = LDQ_NQ_BASE + P;
+  const int nprobes_total = (int)k.classes.size();
+  const int block = (k.o.probe_block > 0) ? std::min(k.o.probe_block, nprobes_total) : nprobes_total;
+  const bool is3d = Q->ndim == 3;
+  // tiles
+  int tiles_x = 0, tiles_y = 0, nzseg = 0, ntiles = 0;
+  const int zseg = 32;
+  if (is3d)
+    pass3d_tiles((int)Q->shape[0], (int)Q->shape[1], (int)Q->shape[2], zseg, &tiles_x, &tiles_y, &nzseg, &ntiles);
+  else
+    pass2d_tiles((int)Q->shape[0], (int)Q->shape[1], &tiles_x, &ntiles);
+  if ((int64_t)ntiles * block > INT32_MAX) return fail(LDQ_E_UNSUPPORTED, "grid too large");
+  // workspace
+  CHK(c->vec.reserve(4 * (size_t)block * n * sizeof(T)));
+  CHK(c->partials.reserve((size_t)block * ntiles * nq * sizeof(double)));
+  CHK(c->counters.reserve((size_t)block * sizeof(unsigned)));
+  CHK(c->pstate.reserve((size_t)block * sizeof(ProbeState)));
+  CHK(c->sstate.reserve((size_t)block * N * sizeof(ShiftState)));
+  CHK(c->classes.reserve((size_t)nprobes_total * sizeof(int32_t) + 64));
+  CHK(c->terms.reserve((size_t)nprobes_total * (1 + P) * sizeof(double) + 64));
+  CHK(c->stats.reserve(8 * sizeof(int)));
+  CHK(c->sums.reserve(8 * sizeof(double)));
+  CHK(c->shifts.reserve(2 * LDQ_MAXN * sizeof(cplx)));
+  CHK(c->misc.reserve(8 * sizeof(int)));
+  T *vec = c->vec.as<T>();
+  T *bufA_r = vec, *bufA_p = vec + (size_t)block * n, *bufB_r = vec + 2 * (size_t)block * n,
+    *bufB_p = vec + 3 * (size_t)block * n;
+  cplx *dsig = c->shifts.as<cplx>(), *dcoef = dsig + LDQ_MAXN;
+  HIPCHK(launch_shifts(k.lmin, k.lmax, N, dsig, dcoef, c->stream));
+  HIPCHK(hipMemsetAsync(c->counters.ptr, 0, (size_t)block * sizeof(unsigned), c->stream));
+  HIPCHK(hipMemsetAsync(c->stats.ptr, 0, 8 * sizeof(int), c->stream));
+  HIPCHK(hipMemcpyAsync(c->classes.ptr, k.classes.data(), nprobes_total * sizeof(int32_t), hipMemcpyHostToDevice,
+                        c->stream));
+  int *active_count = c->misc.as<int>();
+
+  TailArgs ta{};
+  ta.partials = c->partials.as<double>();
+  ta.counters = c->counters.as<unsigned>();
+  ta.st = c->pstate.as<ProbeState>();
+  ta.sh = c->sstate.as<ShiftState>();
+  ta.sigma = dsig;
+  ta.nshifts = N;
+  ta.ngrad = P;
+  ta.tol2 = k.o.tol * k.o.tol;
+  const double gt = k.o.grad_tol > 0.0 ? k.o.grad_tol : k.o.tol;
+  ta.grad_tol2 = gt * gt;
+  ta.max_iter = k.o.max_iter;
+  ta.active_count = active_count;
+
+  GradTerm<T> grads[LDQ_MAXP] = {};
+  CHK(fill_grad_terms<T>(k, grads));
+  const T *kfield = nullptr, *obs = nullptr;
+  CHK(field_as(Q, &kfield));
+  CHK(obs_as(Q, &obs));
+
+  Pass2D<T> a2{};
+  Pass3D<T> a3{};
+  if (is3d) {
+    a3.nx = (int)Q->shape[0];
+    a3.ny = (int)Q->shape[1];
+    a3.nz = (int)Q->shape[2];
+    a3.tiles_x = tiles_x;
+    a3.tiles_y = tiles_y;
+    a3.zseg = zseg;
+    a3.nzseg = nzseg;
+    a3.ntiles = ntiles;
+    a3.colC = k.col.colours ? 0 : k.col.C;
+    a3.cola = k.col.a;
+    a3.colb = k.col.b;
+    a3.colours = k.col.colours;
+    a3.kappa2 = Q->kappa2;
+    a3.kappa2_field = kfield;
+    a3.scale = Q->scale;
+    for (int i = 0; i < P; ++i) a3.grad[i] = grads[i];
+    a3.tail = ta;
+  } else {
+    a2.nx = (int)Q->shape[0];
+    a2.ny = (int)Q->shape[1];
+    a2.tiles_x = tiles_x;
+    a2.ntiles = ntiles;
+    a2.colC = k.col.colours ? 0 : k.col.C;
+    a2.cola = k.col.a;
+    a2.colours = k.col.colours;
+    a2.kappa2 = Q->kappa2;
+    a2.kappa2_field = kfield;
+    a2.scale = Q->scale;
+    a2.tau = Q->obs9 ? Q->tau : 0.0;
+    a2.obs = obs;
+    for (int i = 0; i < P; ++i) a2.grad[i] = grads[i];
+    a2.tail = ta;
+  }
+  const bool sq = Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN;
+  const bool has_obs = Q->obs9 != nullptr && Q->tau != 0.0;
+  auto launch = [&](int mode, int nprobes, const T *rin, const T *pin, T *rout, T *pout) -> hipError_t {
+    if (is3d) {
+      a3.mode = mode;
+      a3.nprobes = nprobes;
+      a3.r_in = rin;
+      a3.p_in = pin;
+      a3.r_out = rout;
+      a3.p_out = pout;
+      return launch_pass3d<T>(a3, c->stream);
+    }
+    a2.mode = mode;
+    a2.nprobes = nprobes;
+    a2.r_in = rin;
+    a2.p_in = pin;
+    a2.r_out = rout;
+    a2.p_out = pout;
+    return launch_pass2d<T>(a2, sq, has_obs, c->stream);
+  };
+
+  const int check = k.o.check_every > 0 ? k.o.check_every : 16;
+  int64_t passes = 0;
+  bool stalled = false;
+  HIPCHK(hipEventRecord(c->ev0, c->stream));
+  for (int first = 0; first < nprobes_total; first += block) {
+    const int nb = std::min(block, nprobes_total - first);
+    HIPCHK(launch_init_probes(ta.st, nb, c->classes.as<int32_t>() + first, active_count, c->stream));
+    HIPCHK(launch(MODE_INIT, nb, nullptr, nullptr, nullptr, nullptr));
+    HIPCHK(launch(MODE_FIRST, nb, nullptr, nullptr, bufA_r, bufA_p));
+    passes += 2;
+    bool in_a = true;
+    int h_active = nb;
+    int64_t steps = 0;
+    while (h_active > 0) {
+      for (int i = 0; i < check; ++i) {
+        if (in_a)
+          HIPCHK(launch(MODE_STEP, nb, bufA_r, bufA_p, bufB_r, bufB_p));
+        else
+          HIPCHK(launch(MODE_STEP, nb, bufB_r, bufB_p, bufA_r, bufA_p));
+        in_a = !in_a;
+      }
+      passes += check;
+      steps += check;
+      HIPCHK(hipMemcpyAsync(&h_active, active_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      if (steps > (int64_t)k.o.max_iter + 2 * check) {
+        stalled = true;
+        break;
+      }
+    }
+    HIPCHK(launch_probe_terms(ta.st, ta.sh, dcoef, nb, N, P, c->terms.as<double>(), first, c->stats.as<int>(),
+                              c->stream));
+  }
+  HIPCHK(hipEventRecord(c->ev1, c->stream));
+  HIPCHK(launch_sum_terms(c->terms.as<double>(), nprobes_total, 1 + P, c->sums.as<double>(), c->stream));
+  double sums[1 + LDQ_MAXP];
+  int stats[4];
+  HIPCHK(hipMemcpyAsync(sums, c->sums.ptr, (1 + P) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(stats, c->stats.ptr, sizeof stats, hipMemcpyDeviceToHost, c->stream));
+  c->last_terms.resize((size_t)nprobes_total * (1 + P));
+  HIPCHK(hipMemcpyAsync(c->last_terms.data(), c->terms.ptr, c->last_terms.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  c->last_nparams = P;
+  c->last_count = nprobes_total;
+  for (int i = 0; i <= P; ++i) out_sums[i] = sums[i];
+  int64_t iters_total = 0;
+  std::memcpy(&iters_total, stats + 2, sizeof iters_total);
+  if (info) {
+    info->ncolours = nprobes_total;
+    info->iters_max = stats[1];
+    info->iters_total = iters_total;
+    info->lambda_min = k.lmin;
+    info->lambda_max = k.lmax;
+    info->loop_seconds = ms * 1e-3;
+    info->passes = passes;
+    info->probe_passes = iters_total;
+    // vectors: first pass writes r, p; every later pass reads and writes both;
+    // operator fields (kappa2 / derivative diagonals / observation planes) once per launch
+    const double sv = (double)sizeof(T);
+    double fields = 0.0;
+    if (kfield) fields += 1.0;
+    if (has_obs) fields += 9.0;
+    for (int i = 0; i < P; ++i)
+      if (grads[i].kind == GK_DIAG || (grads[i].kind == GK_SHIFTED && grads[i].field)) fields += 1.0;
+    info->bytes_model = sv * (double)n * (4.0 * (double)iters_total - 2.0 * (double)nprobes_total) +
+                        sv * (double)n * fields * (double)(passes - 2);
+    info->max_rel_residual = 0.0;
+  }
+  if (stalled) return fail(LDQ_E_NO_CONVERGENCE, "probes did not stop within max_iter");
+  if (stats[0] == 2) return fail(LDQ_E_NOT_SPD, "the Krylov recurrence met p^T Q p <= 0 or a non-finite value");
+  if (stats[0] == 3) return fail(LDQ_E_NO_CONVERGENCE, "max_iter = %d reached before every shift converged",
+                                 k.o.max_iter);
+  return LDQ_OK;
+}
+
+static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const ldq_op *const *dQ,
+                        const ldq_options *opts) {
+  if (!c || !Q) return fail(LDQ_E_INVALID, "NULL argument");
+  if (Q->ctx != c) return fail(LDQ_E_INVALID, "operator belongs to another context");
+  if (nparams < 0 || nparams > LDQ_MAXP) return fail(LDQ_E_INVALID, "nparams must be in 0..%d", LDQ_MAXP);
+  if (nparams > 0 && !dQ) return fail(LDQ_E_INVALID, "dQ is NULL");
+  k.c = c;
+  k.Q = const_cast<ldq_op *>(Q);
+  k.nparams = nparams;
+  if (opts)
+    k.o = *opts;
+  else
+    ldq_options_default(&k.o);
+  if (k.o.nshifts < 1 || k.o.nshifts > LDQ_MAXN) return fail(LDQ_E_INVALID, "nshifts must be in 1..%d", LDQ_MAXN);
+  if (!(k.o.tol > 0.0) || !(k.o.grad_tol >= 0.0) || k.o.max_iter < 1)
+    return fail(LDQ_E_INVALID, "tol must be > 0, grad_tol >= 0, max_iter >= 1");
+  if (k.o.precision != LDQ_FP64 && k.o.precision != LDQ_MIXED) return fail(LDQ_E_INVALID, "unknown precision");
+  if (Q->kind != OPK_LATTICE)
+    return fail(LDQ_E_UNSUPPORTED, "the Krylov passes are implemented for lattice operators");
+  for (int i = 0; i < nparams; ++i) {
+    if (!dQ[i]) return fail(LDQ_E_INVALID, "dQ[%d] is NULL", i);
+    if (dQ[i]->n != Q->n) return fail(LDQ_E_INVALID, "dQ[%d] has %lld rows, Q has %lld", i, (long long)dQ[i]->n,
+                                      (long long)Q->n);
+    if (dQ[i]->kind == OPK_LATTICE && (dQ[i]->ndim != Q->ndim || dQ[i]->shape[0] != Q->shape[0] ||
+                                       dQ[i]->shape[1] != Q->shape[1] || dQ[i]->shape[2] != Q->shape[2]))
+      return fail(LDQ_E_INVALID, "dQ[%d] is on another lattice", i);
+    if (dQ[i]->kind == OPK_OBSGRAM && Q->ndim != 2) return fail(LDQ_E_INVALID, "observation gram needs 2-D Q");
+    k.dQ[i] = const_cast<ldq_op *>(dQ[i]);
+  }
+  CHK(set_device(c));
+  // a1: colouring and its non-empty classes
+  CHK(resolve_colouring(c, Q, k.o.k, k.o.colouring, k.o.user_colours, k.o.priority, &k.col));
+  {
+    const int C = k.col.ncolours;
+    DevBuf cnt;
+    CHK(cnt.reserve((size_t)C * sizeof(int)));
+    HIPCHK(hipMemsetAsync(cnt.ptr, 0, (size_t)C * sizeof(int), c->stream));
+    const int32_t *dcol = k.col.colours;
+    if (!dcol) {
+      CHK(c->colbuf.reserve(Q->n * 4));
+      HIPCHK(launch_modular_fill(c->colbuf.as<int32_t>(), (int)Q->shape[0], (int)Q->shape[1],
+                                 Q->ndim == 3 ? (int)Q->shape[2] : 1, k.col.C, k.col.a, k.col.b, c->stream));
+      dcol = c->colbuf.as<int32_t>();
+    }
+    HIPCHK(launch_class_count(dcol, Q->n, C, cnt.as<int>(), c->stream));
+    std::vector<int> h(C);
+    HIPCHK(hipMemcpyAsync(h.data(), cnt.ptr, (size_t)C * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    cnt.release();
+    k.classes.clear();
+    for (int j = 0; j < C; ++j)
+      if (h[j] > 0) k.classes.push_back(j);
+  }
+  // a2: enclosure
+  if (k.o.lambda_min > 0.0 && k.o.lambda_max > 0.0) {
+    k.lmin = k.o.lambda_min;
+    k.lmax = k.o.lambda_max;
+    if (!(k.lmax >= k.lmin)) return fail(LDQ_E_ENCLOSURE, "lambda_max < lambda_min");
+  } else {
+    CHK(spectrum(Q, &k.lmin, &k.lmax));
+  }
+  return LDQ_OK;
+}
+
+static int logdet_impl(ldq_ctx *c, const ldq_op *Q, int nparams, const ldq_op *const *dQ, const ldq_options *opts,
+                       double *logdet, double *grad, ldq_info *info) {
+  auto t0 = std::chrono::steady_clock::now();
+  Call k{};
+  CHK(prepare_call(k, c, Q, nparams, dQ, opts));
+  double sums[1 + LDQ_MAXP] = {};
+  ldq_info tmp{};
+  int st = (k.o.precision == LDQ_MIXED) ? run_krylov<float>(k, &tmp, sums) : run_krylov<double>(k, &tmp, sums);
+  if (st != LDQ_OK && st != LDQ_E_NO_CONVERGENCE) return st;
+  if (logdet) *logdet = sums[0];
+  if (grad)
+    for (int i = 0; i < nparams; ++i) grad[i] = sums[1 + i];
+  tmp.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = tmp;
+  return st;
+}
+
+extern "C" int ldq_logdet(ldq_ctx *c, const ldq_op *Q, const ldq_options *opts, double *logdet, ldq_info *info) {
+  if (!logdet) return fail(LDQ_E_INVALID, "logdet is NULL");
+  return logdet_impl(c, Q, 0, nullptr, opts, logdet, nullptr, info);
+}
+
+extern "C" int ldq_logdet_grad(ldq_ctx *c, const ldq_op *Q, int nparams, const ldq_op *const *dQ,
+                               const ldq_options *opts, double *logdet, double *grad, ldq_info *info) {
+  if (!logdet || (nparams > 0 && !grad)) return fail(LDQ_E_INVALID, "NULL output");
+  return logdet_impl(c, Q, nparams, dQ, opts, logdet, grad, info);
+}
+
+extern "C" int ldq_probe_terms(ldq_ctx *c, double *out, int64_t capacity, int64_t *count, int *nparams) {
+  if (!c || !count || !nparams) return fail(LDQ_E_INVALID, "NULL argument");
+  *count = c->last_count;
+  *nparams = c->last_nparams;
+  const int64_t need = c->last_count * (1 + c->last_nparams);
+  if (out) {
+    if (capacity < need) return fail(LDQ_E_INVALID, "capacity %lld < %lld", (long long)capacity, (long long)need);
+    std::memcpy(out, c->last_terms.data(), need * sizeof(double));
+  }
+  return LDQ_OK;
+}
+
+extern "C" int ldq_logdet_batched(ldq_ctx *c, int nfields, const ldq_op *const *Q, int nparams,
+                                  const ldq_op *const *dQ, const ldq_options *opts, double *logdet, double *grad,
+                                  ldq_info *info) {
+  if (!c || nfields < 0 || (nfields > 0 && (!Q || !logdet)) || (nparams > 0 && (!dQ || !grad)))
+    return fail(LDQ_E_INVALID, "invalid batched arguments");
+  int worst = LDQ_OK;
+  for (int f = 0; f < nfields; ++f) {
+    int st = logdet_impl(c, Q[f], nparams, nparams ? dQ + (size_t)f * nparams : nullptr, opts, logdet + f,
+                         nparams ? grad + (size_t)f * nparams : nullptr, info ? info + f : nullptr);
+    if (st != LDQ_OK && st != LDQ_E_NO_CONVERGENCE) return st;
+    if (st != LDQ_OK) worst = st;
+  }
+  return worst;
+}

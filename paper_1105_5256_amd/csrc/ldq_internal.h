@@ -1,0 +1,130 @@
+// Internal types shared by the host driver and the HIP kernels of libldq.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define LDQ_MAXP 4          // derivative operators per call
+#define LDQ_MAXN 64         // shifts per call (one wave64 lane per shift)
+#define LDQ_BLOCK 256       // threads per workgroup of the pass kernels
+#define LDQ_NQ_BASE 3       // reduced quantities of a pass: gamma, delta, rho (+ one omega per parameter)
+
+namespace ldq {
+
+// ---------------------------------------------------------------- complex FP64
+struct cplx {
+  double re, im;
+};
+__host__ __device__ inline cplx cmk(double r, double i) { return cplx{r, i}; }
+__host__ __device__ inline cplx cadd(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline cplx csub(cplx a, cplx b) { return cplx{a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline cplx cmul(cplx a, cplx b) {
+  return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline cplx cscale(cplx a, double s) { return cplx{a.re * s, a.im * s}; }
+__host__ __device__ inline cplx cdiv(cplx a, cplx b) {
+  // Smith's algorithm: avoids overflow of |b|^2 for large or tiny b
+  if (fabs(b.re) >= fabs(b.im)) {
+    double r = b.im / b.re, d = b.re + b.im * r;
+    return cplx{(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+  } else {
+    double r = b.re / b.im, d = b.re * r + b.im;
+    return cplx{(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+  }
+}
+__host__ __device__ inline double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
+
+// ------------------------------------------------------------ per-probe state
+// Scalars of the base CG recurrence of one probe (all FP64).  Iteration k of a
+// pass uses alpha = alpha_k and beta_prev = beta_{k-1}; gamma = r_k . r_k.
+struct ProbeState {
+  double gamma;
+  double alpha;
+  double alpha_prev;
+  double beta_prev;
+  double vnorm2;
+  double grad[LDQ_MAXP];
+  int iter;
+  int active;
+  int status;   // ldq_status of this probe (0 while fine)
+  int colour;   // colour class this probe indicates
+};
+
+// Per (probe, shift) state of the multi-shift recurrence.
+struct ShiftState {
+  cplx zeta, zeta_prev, phi, psi;
+  int frozen;
+  int pad;
+};
+
+// Derivative-operator term applied inside a pass (gradient dot products).
+enum GradKind { GK_DIAG = 1, GK_SHIFTED = 2, GK_OBS = 3 };
+
+template <typename T>
+struct GradTerm {
+  int kind;
+  double scale;
+  double kappa2;          // GK_SHIFTED with a constant shift
+  const T *field;         // GK_DIAG: d[n]; GK_SHIFTED: kappa2 field or null
+  const T *obs;           // GK_OBS: 9 x n coefficient planes
+};
+
+// Shared tail arguments (reduction + multi-shift recurrences).
+struct TailArgs {
+  double *partials;        // [probe][tile][nq]
+  unsigned *counters;      // [probe], zero between passes
+  ProbeState *st;          // [probe]
+  ShiftState *sh;          // [probe][nshifts]
+  const cplx *sigma;       // [nshifts]
+  int nshifts;
+  int ngrad;
+  double tol2;             // tol^2
+  double grad_tol2;        // grad_tol^2
+  int max_iter;
+  int *active_count;       // probes still iterating (decremented by the tails)
+};
+
+enum PassMode { MODE_INIT = 0, MODE_FIRST = 1, MODE_STEP = 2 };
+
+// 2-D lattice pass.
+template <typename T>
+struct Pass2D {
+  int nx, ny;
+  int tiles_x, ntiles;
+  int nprobes;
+  // colouring: modular (C > 0) or array
+  int colC, cola;
+  const int32_t *colours;
+  // operator
+  double kappa2;            // constant shift (SQUARED and unfielded SHIFTED)
+  const T *kappa2_field;    // SHIFTED with a field
+  double scale;             // operator scale
+  double tau;               // observation weight (0: none)
+  const T *obs;             // 9 x n planes of A^T A
+  GradTerm<T> grad[LDQ_MAXP];
+  // vectors, probe-major [probe][n]
+  const T *r_in, *p_in;
+  T *r_out, *p_out;
+  int mode;
+  TailArgs tail;
+};
+
+// 3-D lattice pass (7-point shifted Laplacian, z marched inside a workgroup).
+template <typename T>
+struct Pass3D {
+  int nx, ny, nz;
+  int tiles_x, tiles_y, zseg, nzseg, ntiles;
+  int nprobes;
+  int colC, cola, colb;
+  const int32_t *colours;
+  double kappa2;
+  const T *kappa2_field;
+  double scale;
+  GradTerm<T> grad[LDQ_MAXP];
+  const T *r_in, *p_in;
+  T *r_out, *p_out;
+  int mode;
+  TailArgs tail;
+};
+
+}  // namespace ldq

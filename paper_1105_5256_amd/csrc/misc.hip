@@ -1,0 +1,260 @@
+// Small kernels around the Krylov passes: probe-state initialisation, the
+// final reduction of the estimator, the contour-quadrature shifts, modular
+// colour fills, deterministic min/max/Gershgorin reductions and precision
+// conversion.
+#include "ldq_internal.h"
+
+namespace ldq {
+
+// ------------------------------------------------------------ probe states
+__global__ void init_probes_kernel(ProbeState *st, int nprobes, const int32_t *classes, int *active_count) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < nprobes) {
+    ProbeState ps = {};
+    ps.active = 1;
+    ps.colour = classes[j];
+    st[j] = ps;
+  }
+  if (j == 0) *active_count = nprobes;
+}
+
+hipError_t launch_init_probes(ProbeState *st, int nprobes, const int32_t *classes, int *active_count,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(init_probes_kernel, dim3((nprobes + 255) / 256), dim3(256), 0, s, st, nprobes, classes,
+                     active_count);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- finaliser
+// terms[(first + j) * (1 + ngrad) + 0] = Im sum_l c_l psi_jl and + 1 + i = G_ij
+// for the probes of one block; status/iteration summaries go to stats.
+__global__ void probe_terms_kernel(const ProbeState *st, const ShiftState *sh, const cplx *coef, int nprobes,
+                                   int nshifts, int ngrad, double *terms, int first, int *stats) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nprobes) return;
+  const ShiftState *s = sh + (size_t)j * nshifts;
+  double t = 0.0;
+  for (int l = 0; l < nshifts; ++l) t += coef[l].re * s[l].psi.im + coef[l].im * s[l].psi.re;
+  double *dst = terms + (size_t)(first + j) * (1 + ngrad);
+  dst[0] = t;
+  for (int i = 0; i < ngrad; ++i) dst[1 + i] = st[j].grad[i];
+  // stats: [0] worst status, [1] max iterations, [2..3] total iterations (64-bit)
+  atomicMax(stats + 0, st[j].status);
+  atomicMax(stats + 1, st[j].iter);
+  atomicAdd((unsigned long long *)(stats + 2), (unsigned long long)st[j].iter);
+}
+
+hipError_t launch_probe_terms(const ProbeState *st, const ShiftState *sh, const cplx *coef, int nprobes,
+                              int nshifts, int ngrad, double *terms, int first, int *stats, hipStream_t s) {
+  hipLaunchKernelGGL(probe_terms_kernel, dim3((nprobes + 255) / 256), dim3(256), 0, s, st, sh, coef, nprobes,
+                     nshifts, ngrad, terms, first, stats);
+  return hipGetLastError();
+}
+
+// Sum the per-probe terms in a fixed order: out[c] = sum_j terms[j * ncol + c].
+__global__ void sum_terms_kernel(const double *terms, int nprobes, int ncol, double *out) {
+  __shared__ double red[256];
+  for (int c = 0; c < ncol; ++c) {
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < nprobes; j += 256) acc += terms[(size_t)j * ncol + c];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_sum_terms(const double *terms, int nprobes, int ncol, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_terms_kernel, dim3(1), dim3(256), 0, s, terms, nprobes, ncol, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ shifts
+// Complete elliptic integral K(k) = pi / (2 AGM(1, sqrt(1 - k^2))).
+__device__ double ellip_k(double k) {
+  double a = 1.0, b = sqrt((1.0 - k) * (1.0 + k));
+  for (int i = 0; i < 40 && fabs(a - b) > 1e-16 * a; ++i) {
+    const double an = 0.5 * (a + b);
+    b = sqrt(a * b);
+    a = an;
+  }
+  return M_PI / (2.0 * a);
+}
+
+// Jacobi sn, cn, dn of a real argument u for parameter m = k^2 by the
+// arithmetic-geometric mean and descending Landen transformation
+// (Abramowitz & Stegun 16.4).
+__device__ void ellip_j(double u, double m, double *sn, double *cn, double *dn) {
+  double a[32], c[32];
+  a[0] = 1.0;
+  double b = sqrt(1.0 - m);
+  c[0] = sqrt(m);
+  int nst = 0;
+  while (nst < 30 && fabs(c[nst]) > 1e-17) {
+    const double an = 0.5 * (a[nst] + b);
+    c[nst + 1] = 0.5 * (a[nst] - b);
+    b = sqrt(a[nst] * b);
+    a[nst + 1] = an;
+    ++nst;
+  }
+  double phi = ldexp(a[nst] * u, nst);
+  double phi_prev = phi;
+  for (int i = nst; i >= 1; --i) {
+    phi_prev = phi;
+    phi = 0.5 * (phi + asin(c[i] / a[i] * sin(phi)));
+  }
+  *sn = sin(phi);
+  *cn = cos(phi);
+  *dn = (nst == 0) ? 1.0 : cos(phi) / cos(phi_prev - phi);
+}
+
+// sigma_l = w_l^2 and c_l = (2K / (pi N)) 4 w_l log(w_l) w'(t_l), with
+// w(t) = sqrt(m M)^{1/2} (1/k + sn t) / (1/k - sn t) on the conformal map of
+// the square-root spectrum [sqrt m, sqrt M] and midpoint nodes
+// t_l = -K + i K'/2 + (l - 1/2) 2K / N (eq. (7); Hale, Higham & Trefethen).
+__global__ void shifts_kernel(double lmin, double lmax, int N, cplx *sigma, cplx *coef) {
+  const int l = threadIdx.x;
+  if (l >= N) return;
+  lmax = fmax(lmax, 1.01 * lmin);          // enclosure ratio kept >= 1.01 (see the oracle's note)
+  const double r = sqrt(sqrt(lmax / lmin));
+  const double c0 = sqrt(sqrt(lmin * lmax));
+  const double k = (r - 1.0) / (r + 1.0);
+  const double m = k * k;
+  const double K = ellip_k(k);
+  const double Kp = ellip_k(sqrt((1.0 - k) * (1.0 + k)));
+  const double x = -K + (l + 0.5) * 2.0 * K / N;
+  const double y = 0.5 * Kp;
+  double s, c, d, s1, c1, d1;
+  ellip_j(x, m, &s, &c, &d);
+  ellip_j(y, 1.0 - m, &s1, &c1, &d1);
+  const double den = c1 * c1 + m * s * s * s1 * s1;
+  const cplx sn = cmk(s * d1 / den, c * d * s1 * c1 / den);
+  const cplx cn = cmk(c * c1 / den, -s * d * s1 * d1 / den);
+  const cplx dn = cmk(d * c1 * d1 / den, -m * s * c * s1 / den);
+  const double ik = 1.0 / k;
+  const cplx num = cmk(ik + sn.re, sn.im), dnm = cmk(ik - sn.re, -sn.im);
+  const cplx w = cscale(cdiv(num, dnm), c0);
+  const cplx dw = cscale(cdiv(cmul(cn, dn), cmul(dnm, dnm)), c0 * 2.0 * ik);
+  const cplx logw = cmk(0.5 * log(cabs2(w)), atan2(w.im, w.re));
+  sigma[l] = cmul(w, w);
+  coef[l] = cscale(cmul(cmul(w, logw), dw), (2.0 * K / (M_PI * N)) * 4.0);
+}
+
+hipError_t launch_shifts(double lmin, double lmax, int N, cplx *sigma, cplx *coef, hipStream_t s) {
+  hipLaunchKernelGGL(shifts_kernel, dim3(1), dim3(64), 0, s, lmin, lmax, N, sigma, coef);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- modular colouring
+__global__ void modular_fill_kernel(int32_t *col, int nx, int ny, int nz, int C, int a, int b) {
+  const size_t n = (size_t)nx * ny * nz;
+  for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(s % nx);
+    const size_t t = s / nx;
+    const int y = (int)(t % ny), z = (int)(t / ny);
+    col[s] = (int32_t)(((int64_t)x + (int64_t)a * y + (int64_t)b * z) % C);
+  }
+}
+
+hipError_t launch_modular_fill(int32_t *col, int nx, int ny, int nz, int C, int a, int b, hipStream_t s) {
+  const size_t n = (size_t)nx * ny * nz;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(modular_fill_kernel, dim3(blocks), dim3(256), 0, s, col, nx, ny, nz, C, a, b);
+  return hipGetLastError();
+}
+
+// Count of sites per colour (integer atomics: order-independent).
+__global__ void class_count_kernel(const int32_t *col, size_t n, int C, int *count) {
+  for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (size_t)gridDim.x * blockDim.x) {
+    const int c = col[s];
+    if (c >= 0 && c < C) atomicAdd(count + c, 1);
+  }
+}
+
+hipError_t launch_class_count(const int32_t *col, size_t n, int C, int *count, hipStream_t s) {
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(class_count_kernel, dim3(blocks), dim3(256), 0, s, col, n, C, count);
+  return hipGetLastError();
+}
+
+// Max colour value (for user colour arrays); -1 marks an invalid (negative) colour.
+__global__ void colour_max_kernel(const int32_t *col, size_t n, int *out) {
+  int m = -1;
+  bool neg = false;
+  for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (size_t)gridDim.x * blockDim.x) {
+    m = max(m, col[s]);
+    neg |= col[s] < 0;
+  }
+  atomicMax(out, m);
+  if (neg) atomicMax(out + 1, 1);
+}
+
+hipError_t launch_colour_max(const int32_t *col, size_t n, int *out, hipStream_t s) {
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(colour_max_kernel, dim3(blocks), dim3(256), 0, s, col, n, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ min / max of a field (FP64)
+// Two-stage deterministic reduction: min and max are order independent.
+__global__ void minmax_kernel(const double *v, size_t n, double *out) {
+  __shared__ double smin[256], smax[256];
+  double lo = INFINITY, hi = -INFINITY;
+  for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (size_t)gridDim.x * blockDim.x) {
+    lo = fmin(lo, v[s]);
+    hi = fmax(hi, v[s]);
+  }
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = smin[0];
+    out[2 * blockIdx.x + 1] = smax[0];
+  }
+}
+
+// Gershgorin row sums of a CSR matrix: rowsum[i] = sum_j |a_ij| (scaled), reduced by minmax.
+__global__ void csr_abs_rowsum_kernel(const int32_t *rowptr, const double *val, int64_t n, double *rowsum) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) s += fabs(val[e]);
+    rowsum[i] = s;
+  }
+}
+
+hipError_t launch_minmax(const double *v, size_t n, double *partial /* 2 * 256 */, hipStream_t s) {
+  hipLaunchKernelGGL(minmax_kernel, dim3(256), dim3(256), 0, s, v, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_abs_rowsum(const int32_t *rowptr, const double *val, int64_t n, double *rowsum,
+                                 hipStream_t s) {
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(csr_abs_rowsum_kernel, dim3(blocks), dim3(256), 0, s, rowptr, val, n, rowsum);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- conversion
+__global__ void to_float_kernel(const double *src, float *dst, size_t n) {
+  for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (size_t)gridDim.x * blockDim.x)
+    dst[s] = (float)src[s];
+}
+
+hipError_t launch_to_float(const double *src, float *dst, size_t n, hipStream_t s) {
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(to_float_kernel, dim3(blocks), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace ldq

@@ -1,0 +1,249 @@
+"""GPU parity of the lattice Krylov path against the CPU oracle (through the C ABI).
+
+Every case prints its name before the GPU work starts.  Reference values come
+from oracle/ only; inputs come from paper_1105_5256_amd.workloads.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import colouring, estimator, exact, gradient, lattice, shifts
+from paper_1105_5256_amd import ldq, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ldq.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def modular(shape, radius):
+    C, co = colouring.find_modular(len(shape), radius)
+    return colouring.modular_colouring(shape, C, co)
+
+
+# ------------------------------------------------------------------ shifts
+@pytest.mark.parametrize("lo,hi,N", [(0.10467109, 8.09532891, 20), (0.0025075, 64.8013, 20),
+                                     (1.06e-4, 81.0, 30), (2.0, 2.0, 8), (0.3, 900.0, 64)])
+def test_shifts_match_oracle(ctx, lo, hi, N):
+    say(f"shifts [{lo}, {hi}] N={N}")
+    s, c = ldq.ldq_shifts(ctx.handle, lo, hi, N)
+    so, co = shifts.log_shifts(lo, hi, N)
+    assert np.max(np.abs(s - so) / np.abs(so)) < 1e-11
+    assert np.max(np.abs(c - co) / np.abs(co)) < 1e-11
+
+
+# --------------------------------------------------------------- colouring
+@pytest.mark.parametrize("shape,kind,k", [((64, 64), 1, 2), ((100, 70), 2, 4), ((30, 20, 18), 1, 2),
+                                          ((33, 17, 9), 1, 6)])
+def test_modular_colouring_bit_exact(ctx, shape, kind, k):
+    say(f"modular colouring {shape} kind={kind} k={k}")
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, kind, 0.1))
+    col, C = ldq.ldq_colouring(ctx.handle, Q, k, ldq.LDQ_COLOUR_MODULAR)
+    radius = k * (2 if kind == 2 else 1)
+    Cref, co = colouring.find_modular(len(shape), radius)
+    assert C == Cref
+    assert np.array_equal(col, colouring.modular_colouring(shape, Cref, co))
+
+
+@pytest.mark.parametrize("shape,kind,k,seed", [((40, 30), 1, 2, None), ((37, 23), 1, 3, 7),
+                                               ((26, 21), 2, 2, 11), ((12, 10, 9), 1, 2, 5)])
+def test_greedy_colouring_bit_exact(ctx, shape, kind, k, seed):
+    say(f"greedy colouring {shape} kind={kind} k={k} seed={seed}")
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, kind, 0.1))
+    n = int(np.prod(shape))
+    prio = None if seed is None else workloads.priority(n, seed)
+    col, C = ldq.ldq_colouring(ctx.handle, Q, k, ldq.LDQ_COLOUR_GREEDY, prio)
+    M = lattice.shifted_laplacian(shape, 0.1)
+    Qm = M if kind == 1 else lattice.squared(M)
+    order = None if prio is None else colouring.order_from_priority(prio)
+    ref = colouring.greedy_colouring(Qm, k, order)
+    assert np.array_equal(col, ref)
+    assert C == ref.max() + 1
+
+
+def test_greedy_colouring_of_csr_operator(ctx):
+    say("greedy colouring CSR 31x19 13-point k=2")
+    shape = (31, 19)
+    Qm = lattice.squared(lattice.shifted_laplacian(shape, 0.2)).tocsr()
+    Qm.sort_indices()
+    Q = ctx.op(ldq.ldq_op_csr(ctx.handle, Qm.shape[0], Qm.indptr, Qm.indices, Qm.data))
+    prio = workloads.priority(Qm.shape[0], 3)
+    col, _ = ldq.ldq_colouring(ctx.handle, Q, 2, ldq.LDQ_COLOUR_GREEDY, prio)
+    ref = colouring.greedy_colouring(Qm, 2, colouring.order_from_priority(prio))
+    assert np.array_equal(col, ref)
+
+
+# --------------------------------------------------- 2-D: plain 5-point model
+def test_lattice64_5pt_fp64(ctx):
+    say("64x64 5-point kappa2=0.1, distance-2, N=20, tol 1e-10, FP64")
+    wl = workloads.lattice2d_5pt(64, 0.1, 2)
+    shape = wl["shape"]
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, 0.1))
+    dI = ctx.op(ldq.ldq_op_diag(ctx.handle, np.ones(4096)))
+    opts = ldq.ldq_options_default(k=2, nshifts=20, tol=1e-10, grad_tol=1e-10)
+    val, grad, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dI], opts)
+    terms = ldq.ldq_probe_terms(ctx.handle)
+    col = modular(shape, 2)
+    E, Et = estimator.estimator_dst(shape, 0.1, col, 1)
+    G, Gt = gradient.grad_probing_dst(shape, 0.1, 1, col, [sp.identity(4096)])
+    assert info["ncolours"] == 5
+    assert rel(val, E) < 1e-10
+    assert np.allclose(terms[:, 0], Et, rtol=1e-9, atol=0)
+    assert rel(grad[0], G[0]) < 1e-10
+    assert np.allclose(terms[:, 1], Gt[:, 0], rtol=1e-9)
+
+
+def test_lattice64_identity_probing_is_exact(ctx):
+    say("64x64 5-point identity probing (4096 probes) vs closed form and Cholesky")
+    shape = (64, 64)
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, 0.1))
+    dI = ctx.op(ldq.ldq_op_diag(ctx.handle, np.ones(4096)))
+    opts = ldq.ldq_options_default(colouring=ldq.LDQ_COLOUR_IDENTITY, nshifts=20, tol=1e-10)
+    val, grad, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dI], opts)
+    cf = exact.logdet_closed_form(shape, 0.1, 1)
+    chol = exact.logdet_dense_cholesky(lattice.shifted_laplacian(shape, 0.1))
+    assert info["ncolours"] == 4096
+    assert rel(val, cf) < 1e-6 and rel(val, chol) < 1e-6
+    assert rel(grad[0], gradient.grad_closed_form(shape, 0.1, 1)) < 1e-6
+
+
+# ------------------------------------------- 2-D squared operator (13-point)
+@pytest.mark.parametrize("precision,tol,gtol,bound", [(ldq.LDQ_FP64, 1e-10, 1e-10, 1e-9),
+                                                      (ldq.LDQ_MIXED, 1e-5, 1e-6, 1e-4)])
+def test_squared_ragged_with_gradient(ctx, precision, tol, gtol, bound):
+    shape, kappa2 = (100, 70), 0.05
+    say(f"13-point {shape} kappa2={kappa2} distance-4 precision={precision}")
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, kappa2))
+    dQ = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, kappa2, scale=2.0))
+    opts = ldq.ldq_options_default(k=4, nshifts=20, tol=tol, grad_tol=gtol, precision=precision)
+    val, grad, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
+    terms = ldq.ldq_probe_terms(ctx.handle)
+    M = lattice.shifted_laplacian(shape, kappa2)
+    Qm = lattice.squared(M)
+    col = modular(shape, 8)
+    lo, hi = exact.spectrum_closed_form(shape, kappa2, 2)
+    assert abs(info["lambda_min"] - lo) < 1e-12 * lo and abs(info["lambda_max"] - hi) < 1e-12 * hi
+    s, c = shifts.log_shifts(lo, hi, 20)
+    E, Et = estimator.estimator_rational_direct(Qm, col, s, c)
+    G, Gt = gradient.grad_probing_dst(shape, kappa2, 2, col, [2 * M])
+    print(f"logdet {val!r} oracle {E!r} rel {rel(val, E):.2e}; grad {grad[0]!r} oracle {G[0]!r} "
+          f"rel {rel(grad[0], G[0]):.2e}; iters {info['iters_max']}")
+    assert info["ncolours"] == 41
+    assert rel(val, E) < bound
+    assert rel(grad[0], G[0]) < bound
+    assert np.allclose(terms[:, 0], Et, rtol=10 * bound, atol=bound * abs(E) / 41)
+    assert np.allclose(terms[:, 1], Gt[:, 0], rtol=10 * bound)
+
+
+def test_runs_are_bit_identical(ctx):
+    say("determinism: 13-point 90x77 mixed, twice")
+    shape = (90, 77)
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, 0.1))
+    dQ = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, 0.1, scale=2.0))
+    opts = ldq.ldq_options_default(k=4, tol=1e-5, grad_tol=1e-6, precision=ldq.LDQ_MIXED)
+    a = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
+    ta = ldq.ldq_probe_terms(ctx.handle)
+    b = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
+    tb = ldq.ldq_probe_terms(ctx.handle)
+    assert a[0] == b[0] and a[1][0] == b[1][0]
+    assert np.array_equal(ta, tb)
+
+
+# ----------------------------------------------- 3-D field model (7-point)
+@pytest.mark.parametrize("k,precision,tol,bound", [(2, ldq.LDQ_FP64, 1e-10, 1e-9), (6, ldq.LDQ_MIXED, 1e-5, 1e-4)])
+def test_field3d_with_gradient(ctx, k, precision, tol, bound):
+    shape = (20, 16, 14)
+    say(f"3-D field {shape} distance-{k} precision={precision}")
+    wl = workloads.lattice3d_field(shape=shape, sigma=3.0, seed=3, k=k)
+    k2 = wl["kappa2_field"]
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, 0.0, kappa2_field=k2))
+    d0 = ctx.op(ldq.ldq_op_diag(ctx.handle, wl["dkappa2"][0]))
+    d1 = ctx.op(ldq.ldq_op_diag(ctx.handle, wl["dkappa2"][1]))
+    opts = ldq.ldq_options_default(k=k, nshifts=20, tol=tol, grad_tol=tol, precision=precision)
+    val, grad, info = ldq.ldq_logdet_grad(ctx.handle, Q, [d0, d1], opts)
+    Qm = lattice.shifted_laplacian(shape, k2)
+    col = modular(shape, k)
+    lo, hi = info["lambda_min"], info["lambda_max"]
+    ev = np.linalg.eigvalsh(Qm.toarray())
+    assert lo <= ev[0] and hi >= ev[-1]
+    s, c = shifts.log_shifts(lo, hi, 20)
+    E, _ = estimator.estimator_rational_direct(Qm, col, s, c)
+    G, _ = gradient.grad_probing(Qm, [sp.diags(wl["dkappa2"][0]), sp.diags(wl["dkappa2"][1])], col)
+    print(f"logdet rel {rel(val, E):.2e}, grad rel {rel(grad[0], G[0]):.2e} {rel(grad[1], G[1]):.2e}, "
+          f"iters {info['iters_max']}")
+    assert rel(val, E) < bound
+    assert rel(grad[0], G[0]) < bound and rel(grad[1], G[1]) < bound
+
+
+# ------------------------------------------------- Gauss-linear posterior
+@pytest.mark.parametrize("precision,tol,bound", [(ldq.LDQ_FP64, 1e-10, 1e-9), (ldq.LDQ_MIXED, 1e-5, 1e-4)])
+def test_posterior_with_gradient(ctx, precision, tol, bound):
+    shape = (72, 61)
+    say(f"posterior {shape} 900 observations tau=100 precision={precision}")
+    wl = workloads.posterior2d(shape=shape, nobs=900, seed=4)
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, wl["kappa2"]))
+    ldq.ldq_op_add_obs(Q, wl["corner"], wl["weight"], wl["tau"])
+    dk = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, wl["kappa2"], scale=2.0))
+    dt = ctx.op(ldq.ldq_op_obs_gram(ctx.handle, Q, wl["corner"], wl["weight"]))
+    opts = ldq.ldq_options_default(k=4, nshifts=20, tol=tol, grad_tol=tol, precision=precision)
+    val, grad, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dk, dt], opts)
+    n = shape[0] * shape[1]
+    M = lattice.shifted_laplacian(shape, wl["kappa2"])
+    Qm = lattice.posterior_precision(lattice.squared(M), wl["corner"], wl["weight"], wl["tau"])
+    AtA = lattice.observation_gram(n, wl["corner"], wl["weight"])
+    col = modular(shape, 8)
+    assert colouring.is_valid_colouring(Qm, col, 4)
+    lo, hi = info["lambda_min"], info["lambda_max"]
+    ev = np.linalg.eigvalsh(Qm.toarray())
+    assert lo <= ev[0] and hi >= ev[-1]
+    s, c = shifts.log_shifts(lo, hi, 20)
+    E, _ = estimator.estimator_rational_direct(Qm, col, s, c)
+    G, _ = gradient.grad_probing(Qm, [2 * M, AtA], col)
+    print(f"logdet rel {rel(val, E):.2e}, grad rel {rel(grad[0], G[0]):.2e} {rel(grad[1], G[1]):.2e}, "
+          f"iters {info['iters_max']}")
+    assert rel(val, E) < bound
+    assert rel(grad[0], G[0]) < bound and rel(grad[1], G[1]) < bound
+
+
+# ------------------------------------------------------------ failure paths
+def test_error_paths(ctx):
+    say("error paths")
+    shape = (40, 30)
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, 0.05))
+    with pytest.raises(ldq.LdqError) as e:
+        ldq.ldq_logdet(ctx.handle, Q, ldq.ldq_options_default(k=4, max_iter=3))
+    assert e.value.status == ldq.LDQ_E_NO_CONVERGENCE
+    neg = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, -5.0))
+    with pytest.raises(ldq.LdqError) as e:
+        ldq.ldq_logdet(ctx.handle, neg, ldq.ldq_options_default(k=2))
+    assert e.value.status == ldq.LDQ_E_NOT_SPD
+    with pytest.raises(ldq.LdqError) as e:
+        ldq.ldq_logdet(ctx.handle, Q, ldq.ldq_options_default(k=2, nshifts=0))
+    assert e.value.status == ldq.LDQ_E_INVALID
+    with pytest.raises(ldq.LdqError) as e:
+        ldq.ldq_op_lattice(ctx.handle, (10, 10, 10), ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, 0.1)
+    assert e.value.status == ldq.LDQ_E_UNSUPPORTED
+    # a wrong user enclosure (lambda_max below the spectrum) is not silently accepted as exact:
+    # the quadrature is only valid on the enclosure, so the result must differ measurably
+    lo, hi = ldq.ldq_spectrum_bounds(ctx.handle, Q)
+    good, _ = ldq.ldq_logdet(ctx.handle, Q, ldq.ldq_options_default(k=4))
+    bad, _ = ldq.ldq_logdet(ctx.handle, Q, ldq.ldq_options_default(k=4, lambda_min=lo, lambda_max=hi / 50))
+    assert abs(bad - good) > 1e-6 * abs(good)
