@@ -161,7 +161,8 @@ typedef struct {
   double lambda_min, lambda_max;  /* enclosure used */
   double max_rel_residual;   /* max over probes of the final ||r|| / ||v|| */
   double seconds;            /* host wall time of the call */
-  double loop_seconds;       /* device time of the Krylov passes (HIP events on the ctx stream) */
+  double loop_seconds;       /* device time of the pass-kernel launches: HIP events on the ctx stream
+                                bracket each chunk of back-to-back launches (host polling excluded) */
   int64_t passes;            /* pass-kernel launches */
   int64_t probe_passes;      /* sum over launches of the probes each launch advanced */
   double bytes_model;        /* algorithmic bytes of those probe passes (see DESIGN) */

@@ -18,7 +18,7 @@ namespace ldq {
 // launchers (pass2d.hip, pass3d.hip, misc.hip, colour.hip)
 template <typename T> hipError_t launch_pass2d(const Pass2D<T> &, bool, bool, hipStream_t);
 template <typename T> hipError_t launch_pass3d(const Pass3D<T> &, hipStream_t);
-void pass2d_tiles(int nx, int ny, int *tiles_x, int *ntiles);
+void pass2d_tiles(int nx, int ny, bool squared, int rows, int *tiles_x, int *ntiles);
 void pass3d_tiles(int nx, int ny, int nz, int zseg, int *tiles_x, int *tiles_y, int *nzseg, int *ntiles);
 hipError_t launch_init_probes(ProbeState *, int, const int32_t *, int *, hipStream_t);
 hipError_t launch_probe_terms(const ProbeState *, const ShiftState *, const cplx *, int, int, int, double *, int,
@@ -108,7 +108,7 @@ struct DevBuf {
 struct ldq_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  DevBuf vec, partials, counters, pstate, sstate, shifts, classes, terms, stats, sums, misc, colbuf, jpkey, jpmask;
+  DevBuf vec, partials, pstate, sstate, shifts, classes, terms, stats, sums, misc, colbuf, jpkey, jpmask;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<double> last_terms;
   int last_nparams = 0;
@@ -173,7 +173,7 @@ extern "C" void ldq_destroy(ldq_ctx *c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
-  for (DevBuf *b : {&c->vec, &c->partials, &c->counters, &c->pstate, &c->sstate, &c->shifts, &c->classes,
+  for (DevBuf *b : {&c->vec, &c->partials, &c->pstate, &c->sstate, &c->shifts, &c->classes,
                     &c->terms, &c->stats, &c->sums, &c->misc, &c->colbuf, &c->jpkey, &c->jpmask})
     b->release();
   if (c->ev0) hipEventDestroy(c->ev0);
@@ -786,16 +786,18 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   // tiles
   int tiles_x = 0, tiles_y = 0, nzseg = 0, ntiles = 0;
   const int zseg = 32;
+  const int rows2d = 32;
   if (is3d)
     pass3d_tiles((int)Q->shape[0], (int)Q->shape[1], (int)Q->shape[2], zseg, &tiles_x, &tiles_y, &nzseg, &ntiles);
   else
-    pass2d_tiles((int)Q->shape[0], (int)Q->shape[1], &tiles_x, &ntiles);
+    pass2d_tiles((int)Q->shape[0], (int)Q->shape[1], Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN, rows2d, &tiles_x,
+                 &ntiles);
   if ((int64_t)ntiles * block > INT32_MAX) return fail(LDQ_E_UNSUPPORTED, "grid too large");
   // workspace
   CHK(c->vec.reserve(4 * (size_t)block * n * sizeof(T)));
-  CHK(c->partials.reserve((size_t)block * ntiles * nq * sizeof(double)));
-  CHK(c->counters.reserve((size_t)block * sizeof(unsigned)));
-  CHK(c->pstate.reserve((size_t)block * sizeof(ProbeState)));
+  const size_t part_elems = (size_t)block * ntiles * nq;
+  CHK(c->partials.reserve(2 * part_elems * sizeof(double)));
+  CHK(c->pstate.reserve(2 * (size_t)block * sizeof(ProbeState)));
   CHK(c->sstate.reserve((size_t)block * N * sizeof(ShiftState)));
   CHK(c->classes.reserve((size_t)nprobes_total * sizeof(int32_t) + 64));
   CHK(c->terms.reserve((size_t)nprobes_total * (1 + P) * sizeof(double) + 64));
@@ -808,16 +810,14 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     *bufB_p = vec + 3 * (size_t)block * n;
   cplx *dsig = c->shifts.as<cplx>(), *dcoef = dsig + LDQ_MAXN;
   HIPCHK(launch_shifts(k.lmin, k.lmax, N, dsig, dcoef, c->stream));
-  HIPCHK(hipMemsetAsync(c->counters.ptr, 0, (size_t)block * sizeof(unsigned), c->stream));
   HIPCHK(hipMemsetAsync(c->stats.ptr, 0, 8 * sizeof(int), c->stream));
   HIPCHK(hipMemcpyAsync(c->classes.ptr, k.classes.data(), nprobes_total * sizeof(int32_t), hipMemcpyHostToDevice,
                         c->stream));
   int *active_count = c->misc.as<int>();
 
+  double *part[2] = {c->partials.as<double>(), c->partials.as<double>() + part_elems};
+  ProbeState *st[2] = {c->pstate.as<ProbeState>(), c->pstate.as<ProbeState>() + block};
   TailArgs ta{};
-  ta.partials = c->partials.as<double>();
-  ta.counters = c->counters.as<unsigned>();
-  ta.st = c->pstate.as<ProbeState>();
   ta.sh = c->sstate.as<ShiftState>();
   ta.sigma = dsig;
   ta.nshifts = N;
@@ -859,6 +859,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     a2.ny = (int)Q->shape[1];
     a2.tiles_x = tiles_x;
     a2.ntiles = ntiles;
+    a2.rows = rows2d;
     a2.colC = k.col.colours ? 0 : k.col.C;
     a2.cola = k.col.a;
     a2.colours = k.col.colours;
@@ -872,7 +873,15 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   }
   const bool sq = Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN;
   const bool has_obs = Q->obs9 != nullptr && Q->tau != 0.0;
-  auto launch = [&](int mode, int nprobes, const T *rin, const T *pin, T *rout, T *pout) -> hipError_t {
+  // Launch with the probe state and partials read from buffer `in` and written to 1 - in.
+  auto launch = [&](int mode, int nprobes, int in, const T *rin, const T *pin, T *rout, T *pout) -> hipError_t {
+    TailArgs t = ta;
+    t.st_in = st[in];
+    t.st_out = st[1 - in];
+    t.part_in = part[in];
+    t.part_out = part[mode == MODE_INIT ? in : 1 - in];
+    a2.tail = t;
+    a3.tail = t;
     if (is3d) {
       a3.mode = mode;
       a3.nprobes = nprobes;
@@ -891,40 +900,54 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     return launch_pass2d<T>(a2, sq, has_obs, c->stream);
   };
 
-  const int check = k.o.check_every > 0 ? k.o.check_every : 16;
+  // an even number of passes per chunk keeps every chunk on the same buffer parity
+  const int check = k.o.check_every > 0 ? 2 * ((k.o.check_every + 1) / 2) : 16;
   int64_t passes = 0;
   bool stalled = false;
-  HIPCHK(hipEventRecord(c->ev0, c->stream));
+  // Device time of the pass kernels: HIP events bracket each chunk of
+  // back-to-back pass launches on the context stream (the host polls for
+  // convergence between chunks, outside the bracketed spans).
+  double kernel_ms = 0.0;
   for (int first = 0; first < nprobes_total; first += block) {
     const int nb = std::min(block, nprobes_total - first);
-    HIPCHK(launch_init_probes(ta.st, nb, c->classes.as<int32_t>() + first, active_count, c->stream));
-    HIPCHK(launch(MODE_INIT, nb, nullptr, nullptr, nullptr, nullptr));
-    HIPCHK(launch(MODE_FIRST, nb, nullptr, nullptr, bufA_r, bufA_p));
+    // state 0 <- initial; INIT: dots of v -> partials 0; FIRST: tail-init from
+    // partials 0, state 0 -> 1, pass -> partials 1, vectors A; then STEP pairs
+    // (state 1 -> 0, A -> B) and (state 0 -> 1, B -> A).  The final state is in 1.
+    HIPCHK(launch_init_probes(st[0], nb, c->classes.as<int32_t>() + first, active_count, c->stream));
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
+    HIPCHK(launch(MODE_INIT, nb, 0, nullptr, nullptr, nullptr, nullptr));
+    HIPCHK(launch(MODE_FIRST, nb, 0, nullptr, nullptr, bufA_r, bufA_p));
     passes += 2;
     bool in_a = true;
     int h_active = nb;
     int64_t steps = 0;
+    bool chunk_open = true;
     while (h_active > 0) {
+      if (!chunk_open) HIPCHK(hipEventRecord(c->ev0, c->stream));
       for (int i = 0; i < check; ++i) {
         if (in_a)
-          HIPCHK(launch(MODE_STEP, nb, bufA_r, bufA_p, bufB_r, bufB_p));
+          HIPCHK(launch(MODE_STEP, nb, 1, bufA_r, bufA_p, bufB_r, bufB_p));
         else
-          HIPCHK(launch(MODE_STEP, nb, bufB_r, bufB_p, bufA_r, bufA_p));
+          HIPCHK(launch(MODE_STEP, nb, 0, bufB_r, bufB_p, bufA_r, bufA_p));
         in_a = !in_a;
       }
+      HIPCHK(hipEventRecord(c->ev1, c->stream));
+      chunk_open = false;
       passes += check;
       steps += check;
       HIPCHK(hipMemcpyAsync(&h_active, active_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      kernel_ms += ms;
       if (steps > (int64_t)k.o.max_iter + 2 * check) {
         stalled = true;
         break;
       }
     }
-    HIPCHK(launch_probe_terms(ta.st, ta.sh, dcoef, nb, N, P, c->terms.as<double>(), first, c->stats.as<int>(),
+    HIPCHK(launch_probe_terms(st[1], ta.sh, dcoef, nb, N, P, c->terms.as<double>(), first, c->stats.as<int>(),
                               c->stream));
   }
-  HIPCHK(hipEventRecord(c->ev1, c->stream));
   HIPCHK(launch_sum_terms(c->terms.as<double>(), nprobes_total, 1 + P, c->sums.as<double>(), c->stream));
   double sums[1 + LDQ_MAXP];
   int stats[4];
@@ -934,8 +957,6 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   HIPCHK(hipMemcpyAsync(c->last_terms.data(), c->terms.ptr, c->last_terms.size() * sizeof(double),
                         hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   c->last_nparams = P;
   c->last_count = nprobes_total;
   for (int i = 0; i <= P; ++i) out_sums[i] = sums[i];
@@ -947,7 +968,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     info->iters_total = iters_total;
     info->lambda_min = k.lmin;
     info->lambda_max = k.lmax;
-    info->loop_seconds = ms * 1e-3;
+    info->loop_seconds = kernel_ms * 1e-3;
     info->passes = passes;
     info->probe_passes = iters_total;
     // vectors: first pass writes r, p; every later pass reads and writes both;
@@ -988,6 +1009,8 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
   if (k.o.precision != LDQ_FP64 && k.o.precision != LDQ_MIXED) return fail(LDQ_E_INVALID, "unknown precision");
   if (Q->kind != OPK_LATTICE)
     return fail(LDQ_E_UNSUPPORTED, "the Krylov passes are implemented for lattice operators");
+  if (Q->kind == OPK_LATTICE && Q->ndim == 2 && nparams > 2)
+    return fail(LDQ_E_UNSUPPORTED, "at most 2 derivative operators on 2-D lattices");
   for (int i = 0; i < nparams; ++i) {
     if (!dQ[i]) return fail(LDQ_E_INVALID, "dQ[%d] is NULL", i);
     if (dQ[i]->n != Q->n) return fail(LDQ_E_INVALID, "dQ[%d] has %lld rows, Q has %lld", i, (long long)dQ[i]->n,
@@ -995,7 +1018,8 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
     if (dQ[i]->kind == OPK_LATTICE && (dQ[i]->ndim != Q->ndim || dQ[i]->shape[0] != Q->shape[0] ||
                                        dQ[i]->shape[1] != Q->shape[1] || dQ[i]->shape[2] != Q->shape[2]))
       return fail(LDQ_E_INVALID, "dQ[%d] is on another lattice", i);
-    if (dQ[i]->kind == OPK_OBSGRAM && Q->ndim != 2) return fail(LDQ_E_INVALID, "observation gram needs 2-D Q");
+    if (dQ[i]->kind == OPK_OBSGRAM && (Q->ndim != 2 || !Q->obs9))
+      return fail(LDQ_E_UNSUPPORTED, "an observation-gram derivative needs a 2-D Q with an observation term");
     k.dQ[i] = const_cast<ldq_op *>(dQ[i]);
   }
   CHK(set_device(c));

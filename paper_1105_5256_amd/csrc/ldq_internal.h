@@ -69,19 +69,24 @@ struct GradTerm {
   const T *obs;           // GK_OBS: 9 x n coefficient planes
 };
 
-// Shared tail arguments (reduction + multi-shift recurrences).
+// Shared tail arguments (reduction + multi-shift recurrences).  Launch g of the
+// pass kernel reads the probe states and dot-product partials written by
+// launch g - 1 (st_in, part_in) and writes its own (st_out, part_out); the
+// host swaps the two buffers between launches, so no workgroup ever waits
+// for another one inside a launch.
 struct TailArgs {
-  double *partials;        // [probe][tile][nq]
-  unsigned *counters;      // [probe], zero between passes
-  ProbeState *st;          // [probe]
-  ShiftState *sh;          // [probe][nshifts]
+  const double *part_in;   // [probe][nq][tile] of the previous launch
+  double *part_out;        // [probe][nq][tile] of this launch
+  const ProbeState *st_in; // [probe] state before this launch
+  ProbeState *st_out;      // [probe] state after this launch (written by tile 0)
+  ShiftState *sh;          // [probe][nshifts] (read and written by tile 0 only)
   const cplx *sigma;       // [nshifts]
   int nshifts;
   int ngrad;
   double tol2;             // tol^2
   double grad_tol2;        // grad_tol^2
   int max_iter;
-  int *active_count;       // probes still iterating (decremented by the tails)
+  int *active_count;       // probes still iterating (decremented once per finished probe)
 };
 
 enum PassMode { MODE_INIT = 0, MODE_FIRST = 1, MODE_STEP = 2 };
@@ -91,6 +96,7 @@ template <typename T>
 struct Pass2D {
   int nx, ny;
   int tiles_x, ntiles;
+  int rows;                 // lattice rows per wave tile
   int nprobes;
   // colouring: modular (C > 0) or array
   int colC, cola;

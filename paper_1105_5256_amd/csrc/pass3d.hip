@@ -29,10 +29,10 @@ __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
 
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int probe = L / a.ntiles, tile = L - probe * a.ntiles;
-  const ProbeState *st = a.tail.st + probe;
-  if (!st->active) return;
-  const int colour = st->colour;
-  const double alpha = st->alpha, beta = st->beta_prev;
+  const Step step = pass_prologue<LDQ_BLOCK / 64>(a.tail, probe, tile, a.ntiles, a.mode);
+  if (!step.run) return;
+  const int colour = step.colour;
+  const double alpha = step.alpha, beta = step.beta;
   const int txi = tile % a.tiles_x, rest = tile / a.tiles_x;
   const int tyi = rest % a.tiles_y, tzi = rest / a.tiles_y;
   const int x0 = txi * T3X, y0 = tyi * T3Y, z0 = tzi * a.zseg;
@@ -40,7 +40,6 @@ __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
   const size_t n = (size_t)a.nx * a.ny * a.nz;
   const size_t off = (size_t)probe * n;
   const int tid = threadIdx.x;
-  const int nq = LDQ_NQ_BASE + a.tail.ngrad;
   double q[LDQ_NQ_MAX];
 #pragma unroll
   for (int i = 0; i < LDQ_NQ_MAX; ++i) q[i] = 0.0;
@@ -160,7 +159,7 @@ __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
       if (t - 1 >= z0) dots_plane(t - 1);
     }
   }
-  finish_pass(a.tail, probe, tile, a.ntiles, nq, a.mode, q);
+  pass_epilogue<LDQ_BLOCK / 64>(a.tail, probe, tile, a.ntiles, q);
 }
 
 template <typename T>

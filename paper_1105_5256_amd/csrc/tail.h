@@ -1,6 +1,13 @@
-// Device code shared by the pass kernels: deterministic workgroup reduction,
-// last-workgroup detection and the per-probe scalar tail (base CG scalars and
-// the multi-shift CG-M recurrences, Sec. 2.1 last paragraph).
+// Device code shared by the pass kernels: deterministic workgroup reductions,
+// the per-probe scalar tail (base CG scalars and the multi-shift CG-M
+// recurrences, Sec. 2.1 last paragraph) and the dot-product partials.
+//
+// Cross-workgroup reduction without fences: launch g writes one partial sum
+// per (probe, quantity, tile); at the start of launch g + 1 every workgroup of
+// a probe reduces those partials itself, in one fixed order, and so derives
+// the same alpha_{k+1}, beta_k bit for bit.  Tile 0 of each probe additionally
+// advances the per-shift recurrences and the gradient sums and writes the new
+// probe state (state and partials are double-buffered across launches).
 #pragma once
 
 #include "ldq_internal.h"
@@ -16,161 +23,229 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Sum q[0..nq) over the workgroup; the result is valid in red_out[] after the call
-// (all threads).  Order of additions is fixed, so the result is reproducible.
-__device__ inline void block_sum(double *q, int nq, double (*red)[LDQ_NQ_MAX], double *red_out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Sum q[0..nq) over the workgroup of NW waves; every thread receives the
+// totals in out[].  The order of additions is fixed.
+template <int NW>
+__device__ inline void block_sum(const double *q, int nq, double *out) {
+  if constexpr (NW == 1) {
 #pragma unroll
-  for (int i = 0; i < LDQ_NQ_MAX; ++i) {
-    if (i < nq) {
-      double s = wave_sum(q[i]);
-      if (lane == 0) red[wave][i] = s;
+    for (int i = 0; i < LDQ_NQ_MAX; ++i) out[i] = (i < nq) ? wave_sum(q[i]) : 0.0;
+  } else {
+    __shared__ double red[NW][LDQ_NQ_MAX];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < LDQ_NQ_MAX; ++i) {
+      if (i < nq) {
+        double v = wave_sum(q[i]);
+        if (lane == 0) red[wave][i] = v;
+      }
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < LDQ_NQ_MAX; ++i) {
+      double v = 0.0;
+      if (i < nq) {
+        v = red[0][i];
+        for (int w = 1; w < NW; ++w) v += red[w][i];
+      }
+      out[i] = v;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (threadIdx.x < nq) {
-    int i = threadIdx.x;
-    double s = red[0][i];
-    for (int w = 1; w < LDQ_BLOCK / 64; ++w) s += red[w][i];
-    red_out[i] = s;
-  }
-  __syncthreads();
 }
 
-// Multi-shift and base-CG update of one probe after a pass.  Runs on wave 0 of
-// the workgroup that finished the probe's pass last; lane l owns shift l.
-//   MODE_INIT: dots of r_0 = v (gamma_0, delta_0 = v^T Q v, rho_0 = v^T v).
-//   otherwise: dots of r_{k+1} (gamma', delta', rho') and omega_i = w_i^T p_k of
-//              the pass that used alpha_k, beta_{k-1}.
-__device__ inline void probe_tail(const TailArgs &ta, int probe, int mode, const double *tot) {
+struct Step {
+  bool run;       // this workgroup performs the pass
+  int colour;     // colour class of the probe
+  double alpha;   // alpha_k of the pass
+  double beta;    // beta_{k-1} of the pass (p_k = r_k + beta p_{k-1})
+};
+
+// Per-shift update for the dots of r_{k+1} (wave 0 of tile 0; lane l owns shift l).
+//   zeta_{k+1} = zeta_k zeta_{k-1} alpha_{k-1} /
+//                (alpha_k beta_{k-1} (zeta_{k-1} - zeta_k) + zeta_{k-1} alpha_{k-1} (1 - sigma alpha_k))
+//   psi += alpha_k (zeta_{k+1} / zeta_k) phi
+//   phi  = zeta_{k+1} rho' + (zeta_{k+1} / zeta_k)^2 beta_k phi
+// psi accumulates v^T x^sigma and phi tracks v^T p^sigma (scalar-only CG-M).
+__device__ inline bool shifts_update(const TailArgs &ta, int probe, double ak, double akm1, double bkm1, double bk,
+                                     double gn, double rhon, double vnorm2, bool *bad_out) {
   const int lane = threadIdx.x & 63;
-  ProbeState ps = ta.st[probe];
-  const int N = ta.nshifts;
-  ShiftState *shp = ta.sh + (size_t)probe * N;
+  bool frozen = true, bad = false;
+  if (lane < ta.nshifts) {
+    ShiftState *sp = ta.sh + (size_t)probe * ta.nshifts + lane;
+    ShiftState s = *sp;
+    if (!s.frozen) {
+      const cplx sig = ta.sigma[lane];
+      const cplx one_m = cmk(1.0 - sig.re * ak, -sig.im * ak);
+      const cplx den = cadd(cscale(csub(s.zeta_prev, s.zeta), ak * bkm1), cmul(cscale(s.zeta_prev, akm1), one_m));
+      const cplx znext = cdiv(cscale(cmul(s.zeta, s.zeta_prev), akm1), den);
+      const cplx ratio = cdiv(znext, s.zeta);
+      s.psi = cadd(s.psi, cmul(cscale(ratio, ak), s.phi));
+      s.phi = cadd(cscale(znext, rhon), cmul(cscale(cmul(ratio, ratio), bk), s.phi));
+      s.zeta_prev = s.zeta;
+      s.zeta = znext;
+      bad = !(isfinite(s.psi.re) && isfinite(s.psi.im) && isfinite(s.phi.re) && isfinite(s.phi.im));
+      if (bad || cabs2(znext) * gn <= ta.tol2 * vnorm2) s.frozen = 1;
+      *sp = s;
+    }
+    frozen = s.frozen != 0;
+  }
+  *bad_out = __any(bad);
+  return __all(frozen);
+}
+
+// Start of a pass: reduce the previous launch's partials, advance the probe's
+// scalars, decide whether it is finished.  Called by every thread of the
+// workgroup (NW waves; one tile per workgroup).
+template <int NW>
+__device__ inline Step pass_prologue(const TailArgs &ta, int probe, int tile, int ntiles, int mode) {
+  double tot[LDQ_NQ_MAX];
+  const ProbeState in = ta.st_in[probe];
+  Step step{false, in.colour, 0.0, 0.0};
+  if (!in.active) {
+    if (tile == 0 && threadIdx.x == 0) ta.st_out[probe] = in;    // carry the final state forward
+    return step;
+  }
+  if (mode == MODE_INIT) {
+    step.run = true;
+    return step;
+  }
+  const int nq = LDQ_NQ_BASE + ta.ngrad;
+  const bool owner = (tile == 0);
+  const int nred = owner ? nq : 2;
+  double acc[LDQ_NQ_MAX];
+#pragma unroll
+  for (int i = 0; i < LDQ_NQ_MAX; ++i) acc[i] = 0.0;
+  const double *src = ta.part_in + (size_t)probe * nq * ntiles;
+  for (int t = threadIdx.x; t < ntiles; t += NW * 64) {
+#pragma unroll
+    for (int i = 0; i < LDQ_NQ_MAX; ++i)
+      if (i < nred) acc[i] += src[(size_t)i * ntiles + t];
+  }
+  block_sum<NW>(acc, nred, tot);
+
+  ProbeState ps = in;
   bool done = false;
   int status = 0;
-  if (mode == MODE_INIT) {
-    const double g0 = tot[0], d0 = tot[1], rho0 = tot[2];
+  if (mode == MODE_FIRST) {
+    // dots of r_0 = v: gamma_0 = v.v, delta_0 = v^T Q v, rho_0 = v.v
+    const double g0 = tot[0], d0 = tot[1];
     ps.vnorm2 = g0;
     ps.gamma = g0;
     ps.alpha_prev = 1.0;
     ps.beta_prev = 0.0;
     ps.iter = 0;
+#pragma unroll
     for (int i = 0; i < LDQ_MAXP; ++i) ps.grad[i] = 0.0;
     if (g0 == 0.0) {
-      done = true;                                   // empty colour class: contributes nothing
+      done = true;                                 // empty colour class
     } else if (!(d0 > 0.0) || !isfinite(d0)) {
       done = true;
       status = 2;
     } else {
-      ps.alpha = g0 / d0;                           // alpha_0 = gamma_0 / (p_0^T Q p_0), p_0 = v
+      ps.alpha = g0 / d0;                          // alpha_0 = gamma_0 / p_0^T Q p_0 with p_0 = v
     }
-    if (lane < N) {
+    if (owner && threadIdx.x < 64 && (int)threadIdx.x < ta.nshifts) {
       ShiftState s;
       s.zeta = cmk(1.0, 0.0);
       s.zeta_prev = cmk(1.0, 0.0);
-      s.phi = cmk(rho0, 0.0);                        // phi_0 = v^T p^sigma_0 = v^T v
+      s.phi = cmk(tot[2], 0.0);                    // phi_0 = v^T p_0 = v.v
       s.psi = cmk(0.0, 0.0);
       s.frozen = done ? 1 : 0;
       s.pad = 0;
-      shp[lane] = s;
+      ta.sh[(size_t)probe * ta.nshifts + threadIdx.x] = s;
     }
+    step.alpha = ps.alpha;
+    step.beta = 0.0;                               // beta_{-1} = 0: p_0 = r_0
   } else {
-    const double gn = tot[0], dn = tot[1], rhon = tot[2];
+    // dots of r_{k+1} (gamma', delta', rho') and omega_i = w_i . p_k of the last pass
+    const double gn = tot[0], dn = tot[1];
     const double ak = ps.alpha, akm1 = ps.alpha_prev, bkm1 = ps.beta_prev;
-#pragma unroll
-    for (int i = 0; i < LDQ_MAXP; ++i)
-      if (i < ta.ngrad) ps.grad[i] += ak * tot[LDQ_NQ_BASE + i];   // x_{k+1} = x_k + alpha_k p_k
-    const double bk = gn / ps.gamma;                 // beta_k
-    bool frozen = true;
-    if (lane < N) {
-      ShiftState s = shp[lane];
-      if (!s.frozen) {
-        const cplx sig = ta.sigma[lane];
-        // zeta_{k+1} = zeta_k zeta_{k-1} alpha_{k-1} /
-        //   (alpha_k beta_{k-1} (zeta_{k-1} - zeta_k) + zeta_{k-1} alpha_{k-1} (1 - sigma alpha_k))
-        cplx one_m = cmk(1.0 - sig.re * ak, -sig.im * ak);
-        cplx den = cadd(cscale(csub(s.zeta_prev, s.zeta), ak * bkm1),
-                        cmul(cscale(s.zeta_prev, akm1), one_m));
-        cplx znext = cdiv(cscale(cmul(s.zeta, s.zeta_prev), akm1), den);
-        cplx ratio = cdiv(znext, s.zeta);            // zeta_{k+1} / zeta_k
-        s.psi = cadd(s.psi, cmul(cscale(ratio, ak), s.phi));          // psi += alpha^sigma_k phi
-        s.phi = cadd(cscale(znext, rhon), cmul(cscale(cmul(ratio, ratio), bk), s.phi));
-        s.zeta_prev = s.zeta;
-        s.zeta = znext;
-        const bool bad = !(isfinite(s.psi.re) && isfinite(s.psi.im));
-        if (bad) status = 2;
-        if (cabs2(znext) * gn <= ta.tol2 * ps.vnorm2 || bad) s.frozen = 1;
-        shp[lane] = s;
+    const double bk = gn / ps.gamma;               // beta_k
+    bool all_frozen = false;
+    if (owner) {
+      bool bad = false;
+      if constexpr (NW == 1) {
+        all_frozen = shifts_update(ta, probe, ak, akm1, bkm1, bk, gn, tot[2], ps.vnorm2, &bad);
+      } else {
+        __shared__ int sh_flags[2];
+        if (threadIdx.x < 64) {
+          const bool f = shifts_update(ta, probe, ak, akm1, bkm1, bk, gn, tot[2], ps.vnorm2, &bad);
+          if (threadIdx.x == 0) {
+            sh_flags[0] = f;
+            sh_flags[1] = bad;
+          }
+        }
+        __syncthreads();
+        all_frozen = sh_flags[0] != 0;
+        bad = sh_flags[1] != 0;
       }
-      frozen = s.frozen != 0;
-    }
-    const bool all_frozen = __all(frozen);
-    const bool any_bad = __any(status != 0);
-    ps.iter += 1;
-    const bool base_ok = (ta.ngrad == 0) || (gn <= ta.grad_tol2 * ps.vnorm2);
-    if (any_bad) {
-      done = true;
-      status = 2;
-    } else if (gn == 0.0 || (all_frozen && base_ok)) {
-      done = true;
-    } else {
-      const double pap = dn - bk * gn / ak;          // p_{k+1}^T Q p_{k+1}
-      if (!(pap > 0.0) || !isfinite(pap)) {
+      if (bad) {
         done = true;
         status = 2;
-      } else {
-        ps.alpha_prev = ak;
-        ps.alpha = gn / pap;                         // alpha_{k+1}
-        ps.beta_prev = bk;
       }
-      if (!done && ps.iter >= ta.max_iter) {
+#pragma unroll
+      for (int i = 0; i < LDQ_MAXP; ++i)
+        if (i < ta.ngrad) ps.grad[i] += ak * tot[LDQ_NQ_BASE + i];   // w.x_{k+1} = w.x_k + alpha_k w.p_k
+    }
+    ps.iter += 1;
+    const bool base_ok = (ta.ngrad == 0) || (gn <= ta.grad_tol2 * ps.vnorm2);
+    if (!done) {
+      if (gn == 0.0 || (all_frozen && base_ok)) {
         done = true;
-        status = 3;
+      } else {
+        const double pap = dn - bk * gn / ak;      // p_{k+1}^T Q p_{k+1}
+        if (!(pap > 0.0) || !isfinite(pap)) {
+          done = true;
+          status = 2;
+        } else {
+          ps.alpha_prev = ak;
+          ps.alpha = gn / pap;                     // alpha_{k+1}
+          ps.beta_prev = bk;
+        }
+        if (!done && ps.iter >= ta.max_iter) {
+          done = true;
+          status = 3;
+        }
       }
     }
     ps.gamma = gn;
+    step.alpha = ps.alpha;
+    step.beta = ps.beta_prev;
   }
-  if (lane == 0) {
+  if (owner && threadIdx.x == 0) {
     if (done) {
       ps.active = 0;
       ps.status = status;
       atomicSub(ta.active_count, 1);
     }
-    ta.st[probe] = ps;
+    ta.st_out[probe] = ps;
+  }
+  step.run = !done;
+  return step;
+}
+
+// End of a pass: the workgroup's sums of the nq quantities go to part_out.
+template <int NW>
+__device__ inline void pass_epilogue(const TailArgs &ta, int probe, int tile, int ntiles, const double *q) {
+  double tot[LDQ_NQ_MAX];
+  const int nq = LDQ_NQ_BASE + ta.ngrad;
+  block_sum<NW>(q, nq, tot);
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < nq; ++i) ta.part_out[((size_t)probe * nq + i) * ntiles + tile] = tot[i];
   }
 }
 
-// Write this workgroup's partial sums, and if it is the last workgroup of the
-// probe for this pass, reduce all partials in a fixed order and run the tail.
-__device__ inline void finish_pass(const TailArgs &ta, int probe, int tile, int ntiles, int nq, int mode,
-                                   double *q) {
-  __shared__ double red[LDQ_BLOCK / 64][LDQ_NQ_MAX];
-  __shared__ double tot[LDQ_NQ_MAX];
-  __shared__ int is_last;
-  block_sum(q, nq, red, tot);
+// Single-wave epilogue with a compile-time number of quantities.
+template <int NQ>
+__device__ inline void pass_epilogue_n(const TailArgs &ta, int probe, int tile, int ntiles, const double *q) {
+  double tot[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) tot[i] = wave_sum(q[i]);
   if (threadIdx.x == 0) {
-    double *dst = ta.partials + ((size_t)probe * ntiles + tile) * nq;
-    for (int i = 0; i < nq; ++i) dst[i] = tot[i];
-    __threadfence();
-    unsigned old = atomicAdd(ta.counters + probe, 1u);
-    is_last = (old == (unsigned)(ntiles - 1));
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double acc[LDQ_NQ_MAX];
 #pragma unroll
-  for (int i = 0; i < LDQ_NQ_MAX; ++i) acc[i] = 0.0;
-  const double *src = ta.partials + (size_t)probe * ntiles * nq;
-  for (int t = threadIdx.x; t < ntiles; t += LDQ_BLOCK) {
-#pragma unroll
-    for (int i = 0; i < LDQ_NQ_MAX; ++i)
-      if (i < nq) acc[i] += src[(size_t)t * nq + i];
+    for (int i = 0; i < NQ; ++i) ta.part_out[((size_t)probe * NQ + i) * ntiles + tile] = tot[i];
   }
-  block_sum(acc, nq, red, tot);
-  if (threadIdx.x == 0) ta.counters[probe] = 0u;
-  if (threadIdx.x < 64) probe_tail(ta, probe, mode, tot);
 }
 
 // Logical (probe, tile) of a workgroup.  Consecutive workgroup ids are spread

@@ -40,14 +40,21 @@ def modular(shape, radius):
 
 
 # ------------------------------------------------------------------ shifts
-@pytest.mark.parametrize("lo,hi,N", [(0.10467109, 8.09532891, 20), (0.0025075, 64.8013, 20),
-                                     (1.06e-4, 81.0, 30), (2.0, 2.0, 8), (0.3, 900.0, 64)])
-def test_shifts_match_oracle(ctx, lo, hi, N):
+# A degenerate enclosure (lo == hi, widened to a ratio of 1.01 on both sides) has a
+# map modulus of 2.5e-3, where both elliptic-function routes keep ~11 digits.
+@pytest.mark.parametrize("lo,hi,N,bound", [(0.10467109, 8.09532891, 20, 1e-12), (0.0025075, 64.8013, 20, 1e-12),
+                                           (1.06e-4, 81.0, 30, 1e-12), (2.0, 2.0, 8, 1e-10),
+                                           (0.3, 900.0, 64, 1e-12)])
+def test_shifts_match_oracle(ctx, lo, hi, N, bound):
     say(f"shifts [{lo}, {hi}] N={N}")
     s, c = ldq.ldq_shifts(ctx.handle, lo, hi, N)
     so, co = shifts.log_shifts(lo, hi, N)
-    assert np.max(np.abs(s - so) / np.abs(so)) < 1e-11
-    assert np.max(np.abs(c - co) / np.abs(co)) < 1e-11
+    assert np.max(np.abs(s - so) / np.abs(so)) < bound
+    assert np.max(np.abs(c - co) / np.abs(co)) < bound
+    lam = np.geomspace(lo, hi, 50)
+    err_dev = np.max(np.abs(shifts.rational_log(lam, s, c) - np.log(lam)))
+    err_ref = np.max(np.abs(shifts.rational_log(lam, so, co) - np.log(lam)))
+    assert err_dev <= err_ref + 1e-12
 
 
 # --------------------------------------------------------------- colouring
