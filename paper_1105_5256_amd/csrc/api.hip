@@ -16,9 +16,10 @@
 
 namespace ldq {
 // launchers (pass2d.hip, pass3d.hip, misc.hip, colour.hip)
-template <typename T> hipError_t launch_pass2d(const Pass2D<T> &, bool, bool, hipStream_t);
+template <typename T> hipError_t launch_pass2d(const Pass2D<T> &, bool, bool, bool, hipStream_t);
 template <typename T> hipError_t launch_pass3d(const Pass3D<T> &, hipStream_t);
 void pass2d_tiles(int nx, int ny, bool squared, int rows, int *tiles_x, int *ntiles);
+int pass2d_rows(bool squared, int want);
 void pass3d_tiles(int nx, int ny, int nz, int zseg, int *tiles_x, int *tiles_y, int *nzseg, int *ntiles);
 hipError_t launch_init_probes(ProbeState *, int, const int32_t *, int *, hipStream_t);
 hipError_t launch_probe_terms(const ProbeState *, const ShiftState *, const cplx *, int, int, int, double *, int,
@@ -135,6 +136,7 @@ struct ldq_op {
   double *obs9 = nullptr;      // 9 x n planes, FP64
   float *obs9_32 = nullptr;
   double obs_gersh = 0.0;      // max row sum of |A^T A|
+  uint64_t obs_hash = 0;       // FNV-1a of (nobs, corner, weight): equal data gives equal planes
   // CSR
   int64_t nnz = 0;
   int32_t *rowptr = nullptr, *colind = nullptr;
@@ -359,6 +361,18 @@ static int set_obs(ldq_op *op, int64_t nobs, const int32_t *corner, const double
   bool own;
   CHK(upload(op->ctx, planes.data(), planes.size() * sizeof(double), 0, (void **)&op->obs9, &own));
   op->nobs = nobs;
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void *p, size_t bytes) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < bytes; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  };
+  mix(&nobs, sizeof nobs);
+  mix(corner, 4 * (size_t)nobs * sizeof(int32_t));
+  mix(weight, 4 * (size_t)nobs * sizeof(double));
+  op->obs_hash = h;
   return LDQ_OK;
 }
 
@@ -786,7 +800,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   // tiles
   int tiles_x = 0, tiles_y = 0, nzseg = 0, ntiles = 0;
   const int zseg = 32;
-  const int rows2d = 32;
+  const int rows2d = pass2d_rows(Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN, 32);
   if (is3d)
     pass3d_tiles((int)Q->shape[0], (int)Q->shape[1], (int)Q->shape[2], zseg, &tiles_x, &tiles_y, &nzseg, &ntiles);
   else
@@ -873,6 +887,15 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   }
   const bool sq = Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN;
   const bool has_obs = Q->obs9 != nullptr && Q->tau != 0.0;
+  // the specialised 2-D pass: modular colouring, constant kappa2, gradient 0 a
+  // shifted Laplacian with a constant shift, gradient 1 (with observations)
+  // the observation gram of Q's own observations
+  bool fast2d = !is3d && !k.col.colours && !kfield;
+  if (P >= 1) fast2d = fast2d && grads[0].kind == GK_SHIFTED && !grads[0].field;
+  if (P >= 2)
+    fast2d = fast2d && has_obs && grads[1].kind == GK_OBS && k.dQ[1]->obs_hash == Q->obs_hash &&
+             k.dQ[1]->nobs == Q->nobs;
+  if (P >= 2 && fast2d) a2.grad[1].scale = k.dQ[1]->tau;
   // Launch with the probe state and partials read from buffer `in` and written to 1 - in.
   auto launch = [&](int mode, int nprobes, int in, const T *rin, const T *pin, T *rout, T *pout) -> hipError_t {
     TailArgs t = ta;
@@ -897,7 +920,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     a2.p_in = pin;
     a2.r_out = rout;
     a2.p_out = pout;
-    return launch_pass2d<T>(a2, sq, has_obs, c->stream);
+    return launch_pass2d<T>(a2, sq, has_obs, fast2d, c->stream);
   };
 
   // an even number of passes per chunk keeps every chunk on the same buffer parity

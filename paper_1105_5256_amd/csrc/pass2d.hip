@@ -16,18 +16,42 @@
 // (prefetched five rows ahead), and assembles Q p row by row: the contribution
 // of an arriving row to the stencil sums of the rows within distance R is
 // added to a ring of per-row accumulators held in registers; horizontal
-// neighbours come from lane shuffles.  A row of s is complete R steps after it
-// arrives, a row of Q r' another R steps later.  Waves are independent: no LDS
-// arrays and no workgroup barriers.  Dot products are reduced per wave and
-// written as one partial per (probe, quantity, wave tile); the next launch
-// reduces them (tail.h).
+// neighbours come from DPP lane shifts.  A row of s is complete R steps after
+// it arrives, a row of Q r' another R steps later.  Waves are independent: no
+// LDS and no workgroup barriers.  Dot products are reduced per wave and written
+// as one partial per (probe, quantity, wave tile); the next launch reduces them
+// (tail.h).  rows + 4R is a multiple of 5 (the ring length), so the unrolled
+// row loop needs no bounds check.
+#include <type_traits>
+
 #include "ldq_internal.h"
 #include "tail.h"
 
 namespace ldq {
 
-__device__ inline double shfl_d(float v, int src) { return (double)__shfl(v, src, 64); }
-__device__ inline double shfl_d(double v, int src) { return __shfl(v, src, 64); }
+// Lane i receives lane i - 1 (left neighbour column) / lane i + 1 (right).
+// Lanes without a source get 0; the strip edges never use them.
+__device__ inline float from_left(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+}
+__device__ inline float from_right(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+}
+__device__ inline double from_left(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double from_right(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // (A^T A v)(x, yo) from the 9 coefficient planes at site so and the values of
 // v at columns x - 1, x, x + 1 of rows yo - 1 (m), yo (c), yo + 1 (p).
@@ -39,19 +63,20 @@ __device__ inline double obs_apply(const T *o, size_t n, size_t so, T lm, T cm, 
          (double)o[6 * n + so] * (double)lp + (double)o[7 * n + so] * (double)cp + (double)o[8 * n + so] * (double)rp;
 }
 
-template <typename T, int R, bool OBS, int NG>
+template <typename T, int R, bool OBS, int NG, bool GEN>
 __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
   constexpr int W = 64 - 4 * R;
+  constexpr int NQ = LDQ_NQ_BASE + NG;
   const int lane = threadIdx.x;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int probe = L / a.ntiles, tile = L - probe * a.ntiles;
   const Step step = pass_prologue<1>(a.tail, probe, tile, a.ntiles, a.mode);
   if (!step.run) return;
   const int colour = step.colour;
-  const double alpha = a.mode == MODE_INIT ? 0.0 : step.alpha;
+  // GEN: r_k = p_k = v_j generated from the colouring (INIT: alpha = 0, nothing stored)
+  const bool store = !GEN || a.mode != MODE_INIT;
+  const double alpha = (GEN && a.mode == MODE_INIT) ? 0.0 : step.alpha;
   const double beta = step.beta;
-  const bool gen = a.mode != MODE_STEP;          // r_k = p_k = v_j, generated from the colouring
-  const bool store = a.mode != MODE_INIT;
 
   const int nx = a.nx, ny = a.ny;
   const size_t n = (size_t)nx * ny;
@@ -60,64 +85,68 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
   const int x0 = tx * W, y0 = ty * a.rows;
   const int yb = min(y0 + a.rows, ny);
   const int x = x0 - 2 * R + lane;
+  const int xc = min(max(x, 0), nx - 1);           // clamped column: every load address is valid
   const bool xin = x >= 0 && x < nx;
   const bool xout = lane >= 2 * R && lane < 64 - 2 * R && x < nx;   // output column of this strip
-  const int nrows = (yb - y0) + 4 * R;
+  const int nrows = a.rows + 4 * R;                // multiple of 5
   const int ylo = y0 - 2 * R;                      // lattice row of step 0
   const int degx = (x > 0) + (x < nx - 1);
   const double c = a.kappa2 + 4.0;                 // M = (kappa2 + 4) I - (axis neighbours)
-  const int srcL1 = max(lane - 1, 0), srcR1 = min(lane + 1, 63);
-  const int srcL2 = max(lane - 2, 0), srcR2 = min(lane + 2, 63);
 
-  // Modular colouring c(x, y) = (x + a y) mod C, tracked as (x mod C) + (a y mod C).
+  // Modular colouring c(x, y) = (x + a y) mod C = (x mod C + a y mod C) mod C.
+  // The row parts are uniform across the wave and advance by a mod C per row.
   const int C = a.colC;
-  const int cx = (C > 0 && xin) ? x % C : 0;
+  const int cx = (C > 0 && xin) ? x % C : -1 - 2 * C;   // never matches when outside
   const int astep = C > 0 ? a.cola % C : 0;
-  int ay = 0;
-  if (C > 0) {
-    const long t = ((long)a.cola * (long)ylo) % C;
-    ay = (int)(t < 0 ? t + C : t);
-  }
+  auto row_part = [&](int y) -> int {
+    if (C <= 0) return 0;
+    const long t = ((long)a.cola * (long)y) % C;
+    return (int)(t < 0 ? t + C : t);
+  };
+  auto advance = [&](int v) -> int {
+    v += astep;
+    return v >= C ? v - C : v;
+  };
+  auto mine_at = [&](int y, int ay) -> bool {
+    if (C > 0) {
+      int v = cx + ay;
+      v -= (v >= C) ? C : 0;
+      return v == colour;
+    }
+    return xin && y >= 0 && y < ny && a.colours[(size_t)y * nx + xc] == colour;
+  };
+  int ay_in = row_part(ylo);                       // row part of the arriving row
+  int ay_g = row_part(ylo - 1);                    // ... of the gradient row y - 1
+  int ay_d = row_part(ylo - 2 * R);                // ... of the dot-product row y - 2R
 
-  // prefetch queue (five rows ahead): r_k and p_{k-1}, or the generated probe
+  const T *rin = a.r_in + off + xc;
+  const T *pin = a.p_in + off + xc;
+  T *rout = a.r_out + off + xc;
+  T *pout = a.p_out + off + xc;
+
+  // prefetch queue of the next five rows (r_k, p_{k-1})
   T qr[5], qp[5];
-  unsigned qmine = 0;   // bit u: site of prefetch slot u belongs to the probe
   auto fetch = [&](int slot, int i) {
     const int y = ylo + i;
-    const bool in = xin && y >= 0 && y < ny && i < nrows;
-    bool mine = false;
-    if (in) {
-      if (C > 0) {
-        int v = cx + ay;
-        v -= (v >= C) ? C : 0;
-        mine = (v == colour);
-      } else {
-        mine = a.colours[(size_t)y * nx + x] == colour;
-      }
+    T r = T(0), p = T(0);
+    if (!GEN && y >= 0 && y < ny) {
+      const size_t o = (size_t)y * nx;
+      r = rin[o];
+      p = pin[o];
     }
-    if (C > 0) {
-      ay += astep;
-      ay -= (ay >= C) ? C : 0;
-    }
-    if (gen) {
-      qr[slot] = mine ? T(1) : T(0);
-      qp[slot] = T(0);
-    } else {
-      const size_t s = off + (size_t)y * nx + x;
-      qr[slot] = in ? a.r_in[s] : T(0);
-      qp[slot] = in ? a.p_in[s] : T(0);
-    }
-    qmine = (qmine & ~(1u << slot)) | ((mine ? 1u : 0u) << slot);
+    qr[slot] = r;
+    qp[slot] = p;
   };
+  if constexpr (!GEN) {
 #pragma unroll
-  for (int u = 0; u < 5; ++u) fetch(u, u);
+    for (int u = 0; u < 5; ++u) fetch(u, u);
+  }
 
   // rings indexed by lattice row mod 5 (indices are compile-time after unrolling)
   double acc[5], acc2[5], obs_s[5], obs_r[5];
   double macc[NG > 0 ? NG : 1][5];
   T rq[5], pq[5], rnq[5], pl[5], pr[5], rl[5], rr[5];
   double k2q[5];
-  unsigned mine = 0;    // bit (row mod 5): site (x, row) belongs to the probe
 #pragma unroll
   for (int u = 0; u < 5; ++u) {
     acc[u] = acc2[u] = obs_s[u] = obs_r[u] = 0.0;
@@ -126,7 +155,6 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
 #pragma unroll
     for (int g = 0; g < (NG > 0 ? NG : 1); ++g) macc[g][u] = 0.0;
   }
-  constexpr int NQ = LDQ_NQ_BASE + NG;
   double q[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) q[i] = 0.0;
@@ -135,168 +163,432 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
       const int i = i0 + u;
-      if (i < nrows) {
-        const int y = ylo + i;
-        const bool in = xin && y >= 0 && y < ny;
-        // ---- row y arrives: p_k = r_k + beta p_{k-1}, rounded to the storage precision
-        const T r_y = qr[u];
-        const T p_y = gen ? r_y : (T)((double)r_y + beta * (double)qp[u]);
-        mine = (mine & ~(1u << u)) | (qmine & (1u << u));
+      const int y = ylo + i;
+      const bool yin = y >= 0 && y < ny;
+      // ---- row y arrives: p_k = r_k + beta p_{k-1}, rounded to the storage precision
+      T r_y, p_y;
+      if constexpr (GEN) {
+        r_y = (yin && mine_at(y, ay_in)) ? T(1) : T(0);
+        p_y = r_y;
+      } else {
+        r_y = xin ? qr[u] : T(0);
+        p_y = xin ? (T)((double)qr[u] + beta * (double)qp[u]) : T(0);
         fetch(u, i + 5);
-        rq[u] = r_y;
-        pq[u] = p_y;
-        const double p = p_y;
-        const double h1 = shfl_d(p_y, srcL1) + shfl_d(p_y, srcR1);
-        double k2 = a.kappa2;
-        if constexpr (R == 1) {
-          if (a.kappa2_field) k2 = in ? (double)a.kappa2_field[(size_t)y * nx + x] : 0.0;
+      }
+      ay_in = advance(ay_in);
+      rq[u] = r_y;
+      pq[u] = p_y;
+      const double p = p_y;
+      const T pL = from_left(p_y), pR = from_right(p_y);
+      const double h1 = (double)pL + (double)pR;
+      double k2 = a.kappa2;
+      if constexpr (R == 1) {
+        if (a.kappa2_field) k2 = yin ? (double)a.kappa2_field[(size_t)y * nx + xc] : 0.0;
+      }
+      k2q[u] = k2;
+      if constexpr (OBS) {
+        pl[u] = pL;
+        pr[u] = pR;
+      }
+      if constexpr (R == 2) {
+        // M @ M: row y adds p to rows y -+ 2, 2 h1 - 2c p to rows y -+ 1 and
+        // (c^2 + deg) p - 2c h1 + h2 to row y
+        const double h2 = (double)from_left(pL) + (double)from_right(pR);
+        const double c0 = c * c + (double)(degx + (y > 0) + (y < ny - 1));
+        const double t1 = 2.0 * h1 - 2.0 * c * p;
+        acc[(u + 3) % 5] += p;                                      // row y - 2 complete
+        acc[(u + 4) % 5] += t1;
+        acc[u] += c0 * p - 2.0 * c * h1 + h2;
+        acc[(u + 1) % 5] += t1;
+        acc[(u + 2) % 5] = p;                                       // row y + 2 starts
+      } else {
+        // M: row y adds -p to rows y -+ 1 and (kappa2 + 4) p - h1 to row y
+        acc[(u + 4) % 5] -= p;                                      // row y - 1 complete
+        acc[u] += (k2 + 4.0) * p - h1;
+        acc[(u + 1) % 5] = -p;                                      // row y + 1 starts
+      }
+      if constexpr (OBS) {
+        // tau (A^T A p) of row y - 1, from rows y - 2 .. y
+        const int yo = y - 1;
+        double v = 0.0;
+        if (yo >= 0 && yo < ny) {
+          const int um = (u + 3) % 5, uc = (u + 4) % 5;
+          v = obs_apply(a.obs, n, (size_t)yo * nx + xc, pl[um], pq[um], pr[um], pl[uc], pq[uc], pr[uc], pl[u], pq[u],
+                        pr[u]);
         }
-        k2q[u] = k2;
-        if constexpr (OBS) {
-          pl[u] = __shfl(p_y, srcL1, 64);
-          pr[u] = __shfl(p_y, srcR1, 64);
-        }
-        if constexpr (R == 2) {
-          // M @ M: row y adds p to rows y -+ 2, 2 h1 - 2c p to rows y -+ 1 and
-          // (c^2 + deg) p - 2c h1 + h2 to row y
-          const double h2 = shfl_d(p_y, srcL2) + shfl_d(p_y, srcR2);
-          const int deg = degx + (y > 0) + (y < ny - 1);
-          const double t1 = 2.0 * h1 - 2.0 * c * p;
-          acc[(u + 3) % 5] += p;                                      // row y - 2 complete
-          acc[(u + 4) % 5] += t1;
-          acc[u] += (c * c + (double)deg) * p - 2.0 * c * h1 + h2;
-          acc[(u + 1) % 5] += t1;
-          acc[(u + 2) % 5] = p;                                       // row y + 2 starts
-        } else {
-          // M: row y adds -p to rows y -+ 1 and (kappa2 + 4) p - h1 to row y
-          acc[(u + 4) % 5] -= p;                                      // row y - 1 complete
-          acc[u] += (k2 + 4.0) * p - h1;
-          acc[(u + 1) % 5] = -p;                                      // row y + 1 starts
-        }
-        if constexpr (OBS) {
-          // tau (A^T A p) of row y - 1, from rows y - 2 .. y
-          const int yo = y - 1;
-          double v = 0.0;
-          if (xin && yo >= 0 && yo < ny) {
-            const int um = (u + 3) % 5, uc = (u + 4) % 5;
-            v = obs_apply(a.obs, n, (size_t)yo * nx + x, pl[um], pq[um], pr[um], pl[uc], pq[uc], pr[uc], pl[u], pq[u],
-                          pr[u]);
-          }
-          obs_s[(u + 4) % 5] = a.tau * v;
-        }
-        // ---- gradient dots w_g . p_k over the probe's sites of row y - 1
-        {
-          const int yg = y - 1;
-          const int ug = (u + 4) % 5;
-          const bool gout = xout && yg >= y0 && yg < yb && ((mine >> ug) & 1u);
+        obs_s[(u + 4) % 5] = a.tau * v;
+      }
+      // ---- gradient dots w_g . p_k over the probe's sites of row y - 1
+      if constexpr (NG > 0) {
+        const int yg = y - 1;
+        const int ug = (u + 4) % 5;
+        const bool gout = xout && yg >= y0 && yg < yb && mine_at(yg, ay_g);
 #pragma unroll
-          for (int g = 0; g < NG; ++g) {
-            {
-              const GradTerm<T> &gt = a.grad[g];
-              if (gt.kind == GK_SHIFTED) {
-                const double kd = gt.field ? (in ? (double)gt.field[(size_t)y * nx + x] : 0.0) : gt.kappa2;
-                macc[g][ug] -= p;                                     // row y - 1 complete
-                if (gout) q[LDQ_NQ_BASE + g] += gt.scale * macc[g][ug];
-                macc[g][u] += (kd + 4.0) * p - h1;
-                macc[g][(u + 1) % 5] = -p;
-              } else if (gt.kind == GK_DIAG) {
-                if (gout) q[LDQ_NQ_BASE + g] += gt.scale * (double)gt.field[(size_t)yg * nx + x] * (double)pq[ug];
-              } else if constexpr (OBS) {
-                // GK_OBS (the host allows it only when Q has an observation term)
-                if (gout) {
-                  const int um = (u + 3) % 5;
-                  q[LDQ_NQ_BASE + g] += gt.scale * obs_apply(gt.obs, n, (size_t)yg * nx + x, pl[um], pq[um], pr[um],
-                                                             pl[ug], pq[ug], pr[ug], pl[u], pq[u], pr[u]);
-                }
-              }
+        for (int g = 0; g < NG; ++g) {
+          const GradTerm<T> &gt = a.grad[g];
+          if (gt.kind == GK_SHIFTED) {
+            const double kd = gt.field ? (yin ? (double)gt.field[(size_t)y * nx + xc] : 0.0) : gt.kappa2;
+            macc[g][ug] -= p;                                       // row y - 1 complete
+            q[LDQ_NQ_BASE + g] += gout ? gt.scale * macc[g][ug] : 0.0;
+            macc[g][u] += (kd + 4.0) * p - h1;
+            macc[g][(u + 1) % 5] = -p;
+          } else if (gt.kind == GK_DIAG) {
+            if (gout) q[LDQ_NQ_BASE + g] += gt.scale * (double)gt.field[(size_t)yg * nx + xc] * (double)pq[ug];
+          } else if constexpr (OBS) {
+            // GK_OBS (the host allows it only when Q has an observation term)
+            if (gout) {
+              const int um = (u + 3) % 5;
+              q[LDQ_NQ_BASE + g] += gt.scale * obs_apply(gt.obs, n, (size_t)yg * nx + xc, pl[um], pq[um], pr[um],
+                                                         pl[ug], pq[ug], pr[ug], pl[u], pq[u], pr[u]);
             }
           }
         }
-        // ---- row ys = y - R of s = Q p_k is complete: r_{k+1} = r_k - alpha s
-        const int ys = y - R;
-        const int us = (u + 5 - R) % 5;
-        const bool sin = xin && ys >= 0 && ys < ny;
-        double sv = a.scale * acc[us];
-        if constexpr (OBS) sv += obs_s[us];
-        const T rn = sin ? (T)((double)rq[us] - alpha * sv) : T(0);
-        rnq[us] = rn;
-        if (store && xout && ys >= y0 && ys < yb) {
-          const size_t so = off + (size_t)ys * nx + x;
-          a.r_out[so] = rn;
-          a.p_out[so] = pq[us];
-        }
-        // ---- row ys of r_{k+1} enters the Q r' accumulators
-        const double rv = rn;
-        const double g1 = shfl_d(rn, srcL1) + shfl_d(rn, srcR1);
-        if constexpr (OBS) {
-          rl[us] = __shfl(rn, srcL1, 64);
-          rr[us] = __shfl(rn, srcR1, 64);
-        }
-        if constexpr (R == 2) {
-          const double g2 = shfl_d(rn, srcL2) + shfl_d(rn, srcR2);
-          const int deg = degx + (ys > 0) + (ys < ny - 1);
-          const double t1 = 2.0 * g1 - 2.0 * c * rv;
-          acc2[(us + 3) % 5] += rv;                                   // row ys - 2 complete
-          acc2[(us + 4) % 5] += t1;
-          acc2[us] += (c * c + (double)deg) * rv - 2.0 * c * g1 + g2;
-          acc2[(us + 1) % 5] += t1;
-          acc2[(us + 2) % 5] = rv;
-        } else {
-          acc2[(us + 4) % 5] -= rv;                                   // row ys - 1 complete
-          acc2[us] += (k2q[us] + 4.0) * rv - g1;
-          acc2[(us + 1) % 5] = -rv;
-        }
-        if constexpr (OBS) {
-          const int yo = ys - 1;
-          double v = 0.0;
-          if (xin && yo >= 0 && yo < ny) {
-            const int um = (us + 3) % 5, uc = (us + 4) % 5;
-            v = obs_apply(a.obs, n, (size_t)yo * nx + x, rl[um], rnq[um], rr[um], rl[uc], rnq[uc], rr[uc], rl[us],
-                          rnq[us], rr[us]);
-          }
-          obs_r[(us + 4) % 5] = a.tau * v;
-        }
-        // ---- row yd = ys - R of Q r_{k+1} is complete: dot products
-        const int yd = ys - R;
-        const int ud = (us + 5 - R) % 5;
-        if (xout && yd >= y0 && yd < yb) {
-          double qv = a.scale * acc2[ud];
-          if constexpr (OBS) qv += obs_r[ud];
-          const double r2 = rnq[ud];
-          q[0] += r2 * r2;
-          q[1] += r2 * qv;
-          if ((mine >> ud) & 1u) q[2] += r2;
-        }
       }
+      ay_g = advance(ay_g);
+      // ---- row ys = y - R of s = Q p_k is complete: r_{k+1} = r_k - alpha s
+      const int ys = y - R;
+      const int us = (u + 5 - R) % 5;
+      const bool sin = xin && ys >= 0 && ys < ny;
+      double sv = a.scale * acc[us];
+      if constexpr (OBS) sv += obs_s[us];
+      const T rn = sin ? (T)((double)rq[us] - alpha * sv) : T(0);
+      rnq[us] = rn;
+      if (store && xout && ys >= y0 && ys < yb) {
+        const size_t o = (size_t)ys * nx;
+        rout[o] = rn;
+        pout[o] = pq[us];
+      }
+      // ---- row ys of r_{k+1} enters the Q r' accumulators
+      const double rv = rn;
+      const T rL = from_left(rn), rR = from_right(rn);
+      const double g1 = (double)rL + (double)rR;
+      if constexpr (OBS) {
+        rl[us] = rL;
+        rr[us] = rR;
+      }
+      if constexpr (R == 2) {
+        const double g2 = (double)from_left(rL) + (double)from_right(rR);
+        const double c0 = c * c + (double)(degx + (ys > 0) + (ys < ny - 1));
+        const double t1 = 2.0 * g1 - 2.0 * c * rv;
+        acc2[(us + 3) % 5] += rv;                                   // row ys - 2 complete
+        acc2[(us + 4) % 5] += t1;
+        acc2[us] += c0 * rv - 2.0 * c * g1 + g2;
+        acc2[(us + 1) % 5] += t1;
+        acc2[(us + 2) % 5] = rv;
+      } else {
+        acc2[(us + 4) % 5] -= rv;                                   // row ys - 1 complete
+        acc2[us] += (k2q[us] + 4.0) * rv - g1;
+        acc2[(us + 1) % 5] = -rv;
+      }
+      if constexpr (OBS) {
+        const int yo = ys - 1;
+        double v = 0.0;
+        if (yo >= 0 && yo < ny) {
+          const int um = (us + 3) % 5, uc = (us + 4) % 5;
+          v = obs_apply(a.obs, n, (size_t)yo * nx + xc, rl[um], rnq[um], rr[um], rl[uc], rnq[uc], rr[uc], rl[us],
+                        rnq[us], rr[us]);
+        }
+        obs_r[(us + 4) % 5] = a.tau * v;
+      }
+      // ---- row yd = ys - R of Q r_{k+1} is complete: dot products
+      const int yd = ys - R;
+      const int ud = (us + 5 - R) % 5;
+      {
+        const bool dout = xout && yd >= y0 && yd < yb;
+        double qv = a.scale * acc2[ud];
+        if constexpr (OBS) qv += obs_r[ud];
+        const double r2 = dout ? (double)rnq[ud] : 0.0;
+        q[0] += r2 * r2;
+        q[1] += r2 * qv;
+        q[2] += (dout && mine_at(yd, ay_d)) ? r2 : 0.0;
+      }
+      ay_d = advance(ay_d);
     }
   }
   pass_epilogue_n<NQ>(a.tail, probe, tile, a.ntiles, q);
 }
 
-template <typename T, int R, bool OBS>
+// Specialised STEP pass for the common case: modular colouring, constant
+// kappa2, derivative operators fixed at compile time (NG >= 1: g0 is a
+// shifted Laplacian with a constant shift; NG = 2 with OBS: g1 is A^T A with
+// the same planes as Q's observation term).  Every load in the row loop is
+// unconditional (clamped addresses, values selected afterwards), so the
+// compiler can keep the five-row prefetch in flight instead of waiting for all
+// outstanding loads at every conditional.
+template <typename T, int R, bool OBS, int NG>
+__global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
+  constexpr int W = 64 - 4 * R;
+  constexpr int NQ = LDQ_NQ_BASE + NG;
+  const int lane = threadIdx.x;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int probe = L / a.ntiles, tile = L - probe * a.ntiles;
+  const Step step = pass_prologue<1>(a.tail, probe, tile, a.ntiles, MODE_STEP);
+  if (!step.run) return;
+  const int colour = step.colour;
+  const double alpha = step.alpha, beta = step.beta;
+  const T beta_t = (T)beta;
+
+  const int nx = a.nx, ny = a.ny;
+  const size_t n = (size_t)nx * ny;
+  const size_t off = (size_t)probe * n;
+  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const int x0 = tx * W, y0 = ty * a.rows;
+  const int yb = min(y0 + a.rows, ny);
+  const int x = x0 - 2 * R + lane;
+  const int xc = min(max(x, 0), nx - 1);
+  const bool xin = x >= 0 && x < nx;
+  const bool xout = lane >= 2 * R && lane < 64 - 2 * R && x < nx;
+  const int nrows = a.rows + 4 * R;
+  const int ylo = y0 - 2 * R;
+  const int degx = (x > 0) + (x < nx - 1);
+  const double c = a.kappa2 + 4.0;
+  const double m2c = -2.0 * c;
+  const double kd = NG > 0 ? a.grad[0].kappa2 + 4.0 : 0.0;
+  const double gs0 = NG > 0 ? a.grad[0].scale : 0.0;
+  const double gs1 = NG > 1 ? a.grad[1].scale : 0.0;
+  // A tile is interior when every column and every row it touches (prefetch
+  // included) has all four axis neighbours inside the lattice: no masking and
+  // a constant 13-point diagonal there.
+  const bool interior = a.rows == LDQ_ROWS2D && x0 - 2 * R >= 1 && x0 - 2 * R + 63 <= nx - 2 && ylo >= 1 &&
+                        ylo + nrows + 4 <= ny - 2;
+
+  const int C = a.colC;
+  const int cx = xin ? x % C : -1 - 2 * C;
+  const int astep = a.cola % C;
+  auto row_part = [&](int y) -> int {
+    const long t = ((long)a.cola * (long)y) % C;
+    return (int)(t < 0 ? t + C : t);
+  };
+  auto advance = [&](int v) -> int {
+    v += astep;
+    return v >= C ? v - C : v;
+  };
+  auto mine_at = [&](int ay) -> bool {
+    int v = cx + ay;
+    v -= (v >= C) ? C : 0;
+    return v == colour;
+  };
+
+  const T *rin = a.r_in + off + xc;
+  const T *pin = a.p_in + off + xc;
+  T *rout = a.r_out + off + xc;
+  T *pout = a.p_out + off + xc;
+  const T *obs = OBS ? a.obs + xc : nullptr;
+
+  double q[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) q[i] = 0.0;
+
+  auto march = [&](auto interior_tag) {
+    constexpr bool IN = decltype(interior_tag)::value;
+    const double cbase = c * c + (double)degx;       // 13-point diagonal without the row part
+    const double c0in = c * c + 4.0;
+    int ay_g = row_part(ylo - 1);
+    int ay_d = row_part(ylo - 2 * R);
+    T qr[5], qp[5];
+    auto fetch = [&](int slot, int i) {
+      const int yy = ylo + min(i, nrows - 1);
+      const int yc = IN ? yy : min(max(yy, 0), ny - 1);
+      qr[slot] = rin[(size_t)yc * nx];
+      qp[slot] = pin[(size_t)yc * nx];
+    };
+#pragma unroll
+    for (int u = 0; u < 5; ++u) fetch(u, u);
+    double acc[5], acc2[5], obs_s[5], obs_r[5], macc[5];
+    T rq[5], pq[5], rnq[5], pl[5], pr[5], rl[5], rr[5];
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      acc[u] = acc2[u] = obs_s[u] = obs_r[u] = macc[u] = 0.0;
+      rq[u] = pq[u] = rnq[u] = pl[u] = pr[u] = rl[u] = rr[u] = T(0);
+    }
+    auto obs_row = [&](int yo, const T *lm, const T *cm, const T *rm, int um, int uc, int up) -> double {
+      // (A^T A v) of row yo with v rows held in the (l, c, r) rings at slots um, uc, up
+      const int yoc = IN ? yo : min(max(yo, 0), ny - 1);
+      const T *o = obs + (size_t)yoc * nx;
+      const double v = (double)o[0 * n] * (double)lm[um] + (double)o[1 * n] * (double)cm[um] +
+                       (double)o[2 * n] * (double)rm[um] + (double)o[3 * n] * (double)lm[uc] +
+                       (double)o[4 * n] * (double)cm[uc] + (double)o[5 * n] * (double)rm[uc] +
+                       (double)o[6 * n] * (double)lm[up] + (double)o[7 * n] * (double)cm[up] +
+                       (double)o[8 * n] * (double)rm[up];
+      return (IN || (yo >= 0 && yo < ny)) ? v : 0.0;
+    };
+    // Interior tiles of the standard height run the row loop fully unrolled:
+    // every prefetched value is then consumed in straight-line code and the
+    // compiler keeps the loads in flight (a loop back edge would force it to
+    // wait for them).
+    constexpr int NFULL = (IN ? LDQ_ROWS2D + 4 * R : 5);
+    const int nsteps = (IN && nrows == NFULL) ? NFULL : nrows;
+#pragma unroll
+    for (int i0 = 0; i0 < (IN ? NFULL : nsteps); i0 += 5) {
+#pragma unroll
+      for (int u = 0; u < 5; ++u) {
+        const int i = i0 + u;
+        const int y = ylo + i;
+        // ---- row y arrives: p_k = r_k + beta p_{k-1} in the storage precision
+        // (p_k is stored rounded, so one correctly rounded fma matches the
+        // rounding the stored value carries anyway)
+        T r_y = qr[u];
+        T p_y = fma_t(beta_t, qp[u], qr[u]);
+        if constexpr (!IN) {
+          const bool in = xin && y >= 0 && y < ny;
+          r_y = in ? r_y : T(0);
+          p_y = in ? p_y : T(0);
+        }
+        fetch(u, i + 5);
+        rq[u] = r_y;
+        pq[u] = p_y;
+        const double p = p_y;
+        const T pL = from_left(p_y), pR = from_right(p_y);
+        const double h1 = (double)pL + (double)pR;
+        if constexpr (OBS) {
+          pl[u] = pL;
+          pr[u] = pR;
+        }
+        if constexpr (R == 2) {
+          const double h2 = (double)from_left(pL) + (double)from_right(pR);
+          const double c0 = IN ? c0in : cbase + (double)((y > 0) + (y < ny - 1));
+          const double t1 = __builtin_fma(m2c, p, h1 + h1);
+          acc[(u + 3) % 5] += p;
+          acc[(u + 4) % 5] += t1;
+          acc[u] += __builtin_fma(c0, p, __builtin_fma(m2c, h1, h2));
+          acc[(u + 1) % 5] += t1;
+          acc[(u + 2) % 5] = p;
+        } else {
+          acc[(u + 4) % 5] -= p;
+          acc[u] += __builtin_fma(c, p, -h1);
+          acc[(u + 1) % 5] = -p;
+        }
+        double ov = 0.0;                                              // (A^T A p) of row y - 1
+        if constexpr (OBS) {
+          ov = obs_row(y - 1, pl, pq, pr, (u + 3) % 5, (u + 4) % 5, u);
+          obs_s[(u + 4) % 5] = a.tau * ov;
+        }
+        if constexpr (NG > 0) {
+          const int yg = y - 1;
+          const bool gout = xout && yg >= y0 && yg < yb && mine_at(ay_g);
+          macc[(u + 4) % 5] -= p;                                     // (kappa_d^2 + L) p of row y - 1
+          q[LDQ_NQ_BASE] += gout ? gs0 * macc[(u + 4) % 5] : 0.0;
+          macc[u] += __builtin_fma(kd, p, -h1);
+          macc[(u + 1) % 5] = -p;
+          if constexpr (NG > 1 && OBS) q[LDQ_NQ_BASE + 1] += gout ? gs1 * ov : 0.0;
+        }
+        ay_g = advance(ay_g);
+        // ---- row ys = y - R of s = Q p_k is complete: r_{k+1} = r_k - alpha s
+        const int ys = y - R;
+        const int us = (u + 5 - R) % 5;
+        double sv = a.scale * acc[us];
+        if constexpr (OBS) sv += obs_s[us];
+        T rn = (T)__builtin_fma(-alpha, sv, (double)rq[us]);
+        if constexpr (!IN) rn = (xin && ys >= 0 && ys < ny) ? rn : T(0);
+        rnq[us] = rn;
+        if (ys >= y0 && ys < yb) {
+          if (xout) {
+            const size_t o = (size_t)ys * nx;
+            rout[o] = rn;
+            pout[o] = pq[us];
+          }
+        }
+        // ---- row ys of r_{k+1} enters the Q r' accumulators
+        const double rv = rn;
+        const T rL = from_left(rn), rR = from_right(rn);
+        const double g1 = (double)rL + (double)rR;
+        if constexpr (OBS) {
+          rl[us] = rL;
+          rr[us] = rR;
+        }
+        if constexpr (R == 2) {
+          const double g2 = (double)from_left(rL) + (double)from_right(rR);
+          const double c0 = IN ? c0in : cbase + (double)((ys > 0) + (ys < ny - 1));
+          const double t1 = __builtin_fma(m2c, rv, g1 + g1);
+          acc2[(us + 3) % 5] += rv;
+          acc2[(us + 4) % 5] += t1;
+          acc2[us] += __builtin_fma(c0, rv, __builtin_fma(m2c, g1, g2));
+          acc2[(us + 1) % 5] += t1;
+          acc2[(us + 2) % 5] = rv;
+        } else {
+          acc2[(us + 4) % 5] -= rv;
+          acc2[us] += __builtin_fma(c, rv, -g1);
+          acc2[(us + 1) % 5] = -rv;
+        }
+        if constexpr (OBS)
+          obs_r[(us + 4) % 5] = a.tau * obs_row(ys - 1, rl, rnq, rr, (us + 3) % 5, (us + 4) % 5, us);
+        // ---- row yd = ys - R of Q r_{k+1} is complete: dot products
+        const int yd = ys - R;
+        const int ud = (us + 5 - R) % 5;
+        if (yd >= y0 && yd < yb) {
+          double qv = a.scale * acc2[ud];
+          if constexpr (OBS) qv += obs_r[ud];
+          const double r2 = xout ? (double)rnq[ud] : 0.0;
+          q[0] = __builtin_fma(r2, r2, q[0]);
+          q[1] = __builtin_fma(r2, qv, q[1]);
+          q[2] += mine_at(ay_d) ? r2 : 0.0;
+        }
+        ay_d = advance(ay_d);
+      }
+    }
+  };
+  if (interior)
+    march(std::true_type{});
+  else
+    march(std::false_type{});
+  pass_epilogue_n<NQ>(a.tail, probe, tile, a.ntiles, q);
+}
+
+template <typename T, int R, bool OBS, bool GEN>
 static void launch_ng(const Pass2D<T> &a, int nblocks, hipStream_t stream) {
   switch (a.tail.ngrad) {
-    case 0: hipLaunchKernelGGL((pass2d_kernel<T, R, OBS, 0>), dim3(nblocks), dim3(64), 0, stream, a); break;
-    case 1: hipLaunchKernelGGL((pass2d_kernel<T, R, OBS, 1>), dim3(nblocks), dim3(64), 0, stream, a); break;
-    default: hipLaunchKernelGGL((pass2d_kernel<T, R, OBS, 2>), dim3(nblocks), dim3(64), 0, stream, a); break;
+    case 0: hipLaunchKernelGGL((pass2d_kernel<T, R, OBS, 0, GEN>), dim3(nblocks), dim3(64), 0, stream, a); break;
+    case 1: hipLaunchKernelGGL((pass2d_kernel<T, R, OBS, 1, GEN>), dim3(nblocks), dim3(64), 0, stream, a); break;
+    default: hipLaunchKernelGGL((pass2d_kernel<T, R, OBS, 2, GEN>), dim3(nblocks), dim3(64), 0, stream, a); break;
   }
 }
 
-// ngrad <= 2 (checked by the host driver for 2-D lattices)
-template <typename T>
-hipError_t launch_pass2d(const Pass2D<T> &a, bool squared, bool obs, hipStream_t stream) {
-  const int nblocks = a.ntiles * a.nprobes;
+template <typename T, bool GEN>
+static void launch_gen(const Pass2D<T> &a, bool squared, bool obs, int nblocks, hipStream_t stream) {
   if (squared && obs)
-    launch_ng<T, 2, true>(a, nblocks, stream);
+    launch_ng<T, 2, true, GEN>(a, nblocks, stream);
   else if (squared)
-    launch_ng<T, 2, false>(a, nblocks, stream);
+    launch_ng<T, 2, false, GEN>(a, nblocks, stream);
   else
-    launch_ng<T, 1, false>(a, nblocks, stream);
+    launch_ng<T, 1, false, GEN>(a, nblocks, stream);
+}
+
+// ngrad <= 2 (checked by the host driver for 2-D lattices); a.rows + 4R must
+// be a multiple of 5 (pass2d_rows).
+template <typename T>
+hipError_t launch_pass2d(const Pass2D<T> &a, bool squared, bool obs, bool fast, hipStream_t stream) {
+  const int nblocks = a.ntiles * a.nprobes;
+  if (a.mode == MODE_STEP && fast) {
+    const int ng = a.tail.ngrad;
+    if (squared && obs) {
+      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 2, true, 0>), dim3(nblocks), dim3(64), 0, stream, a);
+      else if (ng == 1) hipLaunchKernelGGL((pass2d_fast<T, 2, true, 1>), dim3(nblocks), dim3(64), 0, stream, a);
+      else hipLaunchKernelGGL((pass2d_fast<T, 2, true, 2>), dim3(nblocks), dim3(64), 0, stream, a);
+    } else if (squared) {
+      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 2, false, 0>), dim3(nblocks), dim3(64), 0, stream, a);
+      else hipLaunchKernelGGL((pass2d_fast<T, 2, false, 1>), dim3(nblocks), dim3(64), 0, stream, a);
+    } else {
+      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 1, false, 0>), dim3(nblocks), dim3(64), 0, stream, a);
+      else hipLaunchKernelGGL((pass2d_fast<T, 1, false, 1>), dim3(nblocks), dim3(64), 0, stream, a);
+    }
+  } else if (a.mode == MODE_STEP) {
+    launch_gen<T, false>(a, squared, obs, nblocks, stream);
+  } else {
+    launch_gen<T, true>(a, squared, obs, nblocks, stream);
+  }
   return hipGetLastError();
 }
 
-template hipError_t launch_pass2d<float>(const Pass2D<float> &, bool, bool, hipStream_t);
-template hipError_t launch_pass2d<double>(const Pass2D<double> &, bool, bool, hipStream_t);
+template hipError_t launch_pass2d<float>(const Pass2D<float> &, bool, bool, bool, hipStream_t);
+template hipError_t launch_pass2d<double>(const Pass2D<double> &, bool, bool, bool, hipStream_t);
+
+// Rows per wave tile near `want` with rows + 4R a multiple of 5.
+int pass2d_rows(bool squared, int want) {
+  const int R = squared ? 2 : 1;
+  int rows = want < 1 ? 1 : want;
+  while ((rows + 4 * R) % 5 != 0) ++rows;
+  return rows;
+}
 
 // Wave tiles: 64 - 4R columns by `rows` rows.
 void pass2d_tiles(int nx, int ny, bool squared, int rows, int *tiles_x, int *ntiles) {
