@@ -890,7 +890,8 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   // the specialised 2-D pass: modular colouring, constant kappa2, gradient 0 a
   // shifted Laplacian with a constant shift, gradient 1 (with observations)
   // the observation gram of Q's own observations
-  bool fast2d = !is3d && !k.col.colours && !kfield;
+  bool fast2d = !is3d && !k.col.colours && !kfield && Q->scale == 1.0 &&
+                (double)Q->n * sizeof(T) * (has_obs ? 9.0 : 1.0) < 4294967295.0;
   if (P >= 1) fast2d = fast2d && grads[0].kind == GK_SHIFTED && !grads[0].field;
   if (P >= 2)
     fast2d = fast2d && has_obs && grads[1].kind == GK_OBS && k.dQ[1]->obs_hash == Q->obs_hash &&

@@ -29,25 +29,46 @@
 
 namespace ldq {
 
-// Lane i receives lane i - 1 (left neighbour column) / lane i + 1 (right).
-// Lanes without a source get 0; the strip edges never use them.
+// Lane i receives lane i - 1 (left neighbour column) / lane i + 1 (right)
+// through a DPP wave shift; lanes without a source read 0 (bound_ctrl), and
+// the strip edges never use them.
 __device__ inline float from_left(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
 }
 __device__ inline float from_right(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
 }
 __device__ inline double from_left(double v) {
   const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xF, 0xF, true);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 __device__ inline double from_right(double v) {
   const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xF, 0xF, true);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Buffer accesses: uniform resource and row offset (SGPRs) plus a per-lane
+// byte offset, so no per-lane address arithmetic is needed; accesses outside
+// num_records read 0 / are dropped by the hardware range check.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline float buf_ld(float *, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ inline double buf_ld(double *, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+__device__ inline void buf_st(float v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, vo, so, 0);
+}
+__device__ inline void buf_st(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, 0);
 }
 
 __device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -322,9 +343,10 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
   const int lane = threadIdx.x;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int probe = L / a.ntiles, tile = L - probe * a.ntiles;
+
   const Step step = pass_prologue<1>(a.tail, probe, tile, a.ntiles, MODE_STEP);
   if (!step.run) return;
-  const int colour = step.colour;
+  const int colour = __builtin_amdgcn_readfirstlane(step.colour);
   const double alpha = step.alpha, beta = step.beta;
   const T beta_t = (T)beta;
 
@@ -355,25 +377,31 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
   const int C = a.colC;
   const int cx = xin ? x % C : -1 - 2 * C;
   const int astep = a.cola % C;
+  // (a y) mod C for y >= -5, uniform across the wave (kept in scalar registers)
   auto row_part = [&](int y) -> int {
-    const long t = ((long)a.cola * (long)y) % C;
-    return (int)(t < 0 ? t + C : t);
+    const int ym = ((y % C) + C) % C;
+    return __builtin_amdgcn_readfirstlane((astep * ym) % C);
   };
   auto advance = [&](int v) -> int {
     v += astep;
-    return v >= C ? v - C : v;
+    return __builtin_amdgcn_readfirstlane(v >= C ? v - C : v);
   };
+  // (cx + ay) mod C == colour  <=>  cx == (colour - ay) mod C, a uniform value
   auto mine_at = [&](int ay) -> bool {
-    int v = cx + ay;
-    v -= (v >= C) ? C : 0;
-    return v == colour;
+    int t = colour - ay;
+    t += (t < 0) ? C : 0;
+    return cx == t;
   };
 
-  const T *rin = a.r_in + off + xc;
-  const T *pin = a.p_in + off + xc;
-  T *rout = a.r_out + off + xc;
-  T *pout = a.p_out + off + xc;
-  const T *obs = OBS ? a.obs + xc : nullptr;
+  // buffer resources over this probe's vectors and the observation planes
+  const unsigned vbytes = (unsigned)(n * sizeof(T));
+  const __amdgpu_buffer_rsrc_t rs_rin = make_rsrc(a.r_in + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_pin = make_rsrc(a.p_in + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_rout = make_rsrc(a.r_out + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_pout = make_rsrc(a.p_out + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_obs = make_rsrc(OBS ? a.obs : a.r_in, OBS ? 9u * vbytes : vbytes);
+  const unsigned lx = (unsigned)xc * (unsigned)sizeof(T);           // lane byte offset
+  const unsigned rowb = (unsigned)nx * (unsigned)sizeof(T);         // row stride in bytes
 
   double q[NQ];
 #pragma unroll
@@ -389,8 +417,8 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
     auto fetch = [&](int slot, int i) {
       const int yy = ylo + min(i, nrows - 1);
       const int yc = IN ? yy : min(max(yy, 0), ny - 1);
-      qr[slot] = rin[(size_t)yc * nx];
-      qp[slot] = pin[(size_t)yc * nx];
+      qr[slot] = buf_ld((T *)nullptr, rs_rin, lx, (unsigned)yc * rowb);
+      qp[slot] = buf_ld((T *)nullptr, rs_pin, lx, (unsigned)yc * rowb);
     };
 #pragma unroll
     for (int u = 0; u < 5; ++u) fetch(u, u);
@@ -404,12 +432,16 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
     auto obs_row = [&](int yo, const T *lm, const T *cm, const T *rm, int um, int uc, int up) -> double {
       // (A^T A v) of row yo with v rows held in the (l, c, r) rings at slots um, uc, up
       const int yoc = IN ? yo : min(max(yo, 0), ny - 1);
-      const T *o = obs + (size_t)yoc * nx;
-      const double v = (double)o[0 * n] * (double)lm[um] + (double)o[1 * n] * (double)cm[um] +
-                       (double)o[2 * n] * (double)rm[um] + (double)o[3 * n] * (double)lm[uc] +
-                       (double)o[4 * n] * (double)cm[uc] + (double)o[5 * n] * (double)rm[uc] +
-                       (double)o[6 * n] * (double)lm[up] + (double)o[7 * n] * (double)cm[up] +
-                       (double)o[8 * n] * (double)rm[up];
+      const unsigned so = (unsigned)yoc * rowb;
+      const double v = (double)buf_ld((T *)nullptr, rs_obs, lx, so + 0u * vbytes) * (double)lm[um] +
+                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 1u * vbytes) * (double)cm[um] +
+                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 2u * vbytes) * (double)rm[um] +
+                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 3u * vbytes) * (double)lm[uc] +
+                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 4u * vbytes) * (double)cm[uc] +
+                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 5u * vbytes) * (double)rm[uc] +
+                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 6u * vbytes) * (double)lm[up] +
+                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 7u * vbytes) * (double)cm[up] +
+                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 8u * vbytes) * (double)rm[up];
       return (IN || (yo >= 0 && yo < ny)) ? v : 0.0;
     };
     // Interior tiles of the standard height run the row loop fully unrolled:
@@ -476,16 +508,15 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
         // ---- row ys = y - R of s = Q p_k is complete: r_{k+1} = r_k - alpha s
         const int ys = y - R;
         const int us = (u + 5 - R) % 5;
-        double sv = a.scale * acc[us];
+        double sv = acc[us];                                         // the fast path has scale 1
         if constexpr (OBS) sv += obs_s[us];
         T rn = (T)__builtin_fma(-alpha, sv, (double)rq[us]);
         if constexpr (!IN) rn = (xin && ys >= 0 && ys < ny) ? rn : T(0);
         rnq[us] = rn;
         if (ys >= y0 && ys < yb) {
           if (xout) {
-            const size_t o = (size_t)ys * nx;
-            rout[o] = rn;
-            pout[o] = pq[us];
+            buf_st(rn, rs_rout, lx, (unsigned)ys * rowb);
+            buf_st(pq[us], rs_pout, lx, (unsigned)ys * rowb);
           }
         }
         // ---- row ys of r_{k+1} enters the Q r' accumulators
@@ -516,7 +547,7 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
         const int yd = ys - R;
         const int ud = (us + 5 - R) % 5;
         if (yd >= y0 && yd < yb) {
-          double qv = a.scale * acc2[ud];
+          double qv = acc2[ud];
           if constexpr (OBS) qv += obs_r[ud];
           const double r2 = xout ? (double)rnq[ud] : 0.0;
           q[0] = __builtin_fma(r2, r2, q[0]);
@@ -526,6 +557,7 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
         ay_d = advance(ay_d);
       }
     }
+    return true;
   };
   if (interior)
     march(std::true_type{});
