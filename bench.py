@@ -124,7 +124,7 @@ def main():
     last = infos[-1]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "pass2d_kernel<float, squared, no observations>",
+                "kernel": "pass2d_fast<float, R=2, no observations, 1 gradient> (fused 2-D pass)",
                 "avg_launch_us": round(kern_s / launches * 1e6, 2),
                 "bytes_per_launch": round(kern_bytes / launches),
                 "bytes_model": "16 B per site per active probe (r and p read and written once, FP32)"}
