@@ -89,7 +89,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the probes would shard across GPUs with one scalar all-reduce; see the design notes)",
+              f"(on several GPUs the probes would be split between ranks and their terms summed with one all-reduce of a few doubles; this build measures one GPU)",
               file=sys.stderr)
         sys.exit(2)
     import torch

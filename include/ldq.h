@@ -165,7 +165,9 @@ typedef struct {
                                 bracket each chunk of back-to-back launches (host polling excluded) */
   int64_t passes;            /* pass-kernel launches */
   int64_t probe_passes;      /* sum over launches of the probes each launch advanced */
-  double bytes_model;        /* algorithmic bytes of those probe passes (see DESIGN) */
+  double bytes_model;        /* algorithmic bytes of those passes: r and p read and written once per
+                                probe-site (4 x element size), the first pass writes only, plus each
+                                operator field once per launch */
 } ldq_info;
 
 /* ------------------------------------------------------------- the method */

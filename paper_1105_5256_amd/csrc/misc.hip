@@ -119,7 +119,9 @@ __device__ void ellip_j(double u, double m, double *sn, double *cn, double *dn) 
 __global__ void shifts_kernel(double lmin, double lmax, int N, cplx *sigma, cplx *coef) {
   const int l = threadIdx.x;
   if (l >= N) return;
-  lmax = fmax(lmax, 1.01 * lmin);          // enclosure ratio kept >= 1.01 (see the oracle's note)
+  // a near-degenerate enclosure makes the modulus of the map vanish and the
+  // elliptic functions lose digits; any wider interval still encloses the spectrum
+  lmax = fmax(lmax, 1.01 * lmin);
   const double r = sqrt(sqrt(lmax / lmin));
   const double c0 = sqrt(sqrt(lmin * lmax));
   const double k = (r - 1.0) / (r + 1.0);
