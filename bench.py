@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU reference timing")
-    ap.add_argument("--no-forms", action="store_true", help="skip the FP64-form and accuracy runs")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP64-form, CSR-form and accuracy runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM counters)")
     return ap.parse_args()
@@ -83,6 +83,43 @@ def cpu_baseline(wl, iters_total, sample_iters=200):
                       f"on the 512x512 13-point lattice, {dt:.1f} s, scaled by the workload's "
                       f"{iters_total} probe-iterations; scipy sparse products and numpy updates run "
                       f"single-threaded (BLAS pool {threads} threads, {os.cpu_count()} host cores)"}
+
+
+def csr_forms(ctx, wl, nsteps, ref_val, ref_grad):
+    """The same workload with Q and dQ/dkappa2 given as CSR matrices (the
+    general sparse passes), the same colouring and enclosure as the stencil
+    form, timed in the mixed and FP64 forms."""
+    import torch
+
+    from paper_1105_5256_amd import ldq, workloads
+
+    shape, kappa2 = wl["shape"], wl["kappa2"]
+    n = shape[0] * shape[1]
+    lat = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, kappa2))
+    col, _ = ldq.ldq_colouring(ctx.handle, lat, wl["k"], ldq.LDQ_COLOUR_MODULAR)
+    lo, hi = ldq.ldq_spectrum_bounds(ctx.handle, lat)
+    rp, ci, v = workloads.lattice2d_sq_csr(*shape, kappa2=kappa2)
+    Q = ctx.op(ldq.ldq_op_csr(ctx.handle, n, rp, ci, v))
+    rp, ci, v = workloads.lattice2d_5pt_csr(*shape, kappa2=kappa2, scale=2.0)
+    dQ = ctx.op(ldq.ldq_op_csr(ctx.handle, n, rp, ci, v))
+    res = {}
+    for name, prec, tol, gtol in [("csr_mixed", ldq.LDQ_MIXED, 1e-5, 1e-6), ("csr_fp64", ldq.LDQ_FP64, 1e-5, 1e-6)]:
+        opts = ldq.ldq_options_default(k=wl["k"], nshifts=20, tol=tol, grad_tol=gtol, precision=prec,
+                                       colouring=ldq.LDQ_COLOUR_USER, user_colours=col, lambda_min=lo,
+                                       lambda_max=hi)
+        ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            cv, cg, ci_ = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
+        torch.cuda.synchronize()
+        cdt = (time.perf_counter() - t0) / nsteps
+        res[name] = {"evals_per_s": round(1.0 / cdt, 3), "ms": round(cdt * 1e3, 3),
+                     "gbs": round(ci_["bytes_model"] / ci_["loop_seconds"] / 1e9, 1),
+                     "iters_max": ci_["iters_max"],
+                     "rel_err_vs_tight_fp64": {"logdet": abs(cv - ref_val) / abs(ref_val),
+                                               "grad": abs(cg[0] - ref_grad) / abs(ref_grad)}}
+    return res
 
 
 def main():
@@ -181,7 +218,7 @@ def main():
                      "rel_err_vs_tight_fp64": {"logdet": abs(fv - ref_val) / abs(ref_val),
                                                "grad": abs(fg[0] - ref_grad[0]) / abs(ref_grad[0])}},
         }
-
+        out["forms"].update(csr_forms(ctx, wl, nf, ref_val, ref_grad[0]))
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")    # 1 GiB
         b = torch.empty_like(a)

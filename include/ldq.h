@@ -97,8 +97,13 @@ int ldq_op_lattice(ldq_ctx *ctx, int ndim, const int64_t *shape, int kind, doubl
                    const double *kappa2_field, double scale, unsigned flags, ldq_op **out);
 
 /* General sparse symmetric operator in CSR form (n rows, nnz entries,
- * rowptr[n + 1], colind[nnz] (int32, sorted within a row), val[nnz]).
- * The pattern must be symmetric; the values are used as given. */
+ * rowptr[n + 1], colind[nnz] (int32, strictly ascending within a row),
+ * val[nnz] FP64).  The matrix must be symmetric; host arrays are validated
+ * and copied, LDQ_FLAG_DEVICE_PTR arrays are borrowed unchecked and must keep
+ * their values while the operator lives.  Its log det runs the general sparse
+ * passes: the rows in slices of 64 with the union of the patterns of Q and of
+ * the call's derivative operators (CSR or diagonal), values kept in FP64 in
+ * both precisions (only the Krylov vectors are FP32 in LDQ_MIXED). */
 int ldq_op_csr(ldq_ctx *ctx, int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colind,
                const double *val, unsigned flags, ldq_op **out);
 
@@ -163,11 +168,16 @@ typedef struct {
   double seconds;            /* host wall time of the call */
   double loop_seconds;       /* device time of the pass-kernel launches: HIP events on the ctx stream
                                 bracket each chunk of back-to-back launches (host polling excluded) */
-  int64_t passes;            /* pass-kernel launches */
-  int64_t probe_passes;      /* sum over launches of the probes each launch advanced */
-  double bytes_model;        /* algorithmic bytes of those passes: r and p read and written once per
-                                probe-site (4 x element size), the first pass writes only, plus each
-                                operator field once per launch */
+  int64_t passes;            /* Krylov iterations launched: one fused pass kernel each on lattice
+                                operators; passes A and B and the tail kernel each on CSR operators */
+  int64_t probe_passes;      /* sum over iterations of the probes each advanced */
+  double bytes_model;        /* algorithmic bytes of those passes.  Lattice: r and p read and written
+                                once per probe-site (4 x element size; the first pass writes only),
+                                plus each operator field once per launch.  CSR: 5 x element size per
+                                probe-site (pass A reads and writes r and p, pass B reads r), plus the
+                                sliced operator and the colour array once per pass */
+  int32_t enclosure_violations; /* probes whose Lanczos matrix (from their CG coefficients) has an
+                                   eigenvalue outside [lambda_min, lambda_max] beyond rounding */
 } ldq_info;
 
 /* ------------------------------------------------------------- the method */
@@ -179,7 +189,13 @@ int ldq_colouring(ldq_ctx *ctx, const ldq_op *Q, int k, int method, const int32_
                   int32_t *colours, int32_t *ncolours);
 
 /* a2: enclosure [lambda_min, lambda_max] of the spectrum of Q that the
- * quadrature needs (Sec. 2.1, the paragraph before eq. (7)). */
+ * quadrature needs (Sec. 2.1, the paragraph before eq. (7)).  Lattice
+ * operators: closed-form eigenvalue extremes of the Laplacian, Weyl's bound
+ * for a kappa^2 field, Gershgorin for an observation term.  CSR operators:
+ * lambda_max = the Gershgorin bound, lambda_min = half the smallest eigenvalue
+ * of the Lanczos matrix of 200 CG steps on the all-ones vector; a log det
+ * call lowers it further when a probe's own Lanczos matrix reaches below it,
+ * and keeps the result on the operator. */
 int ldq_spectrum_bounds(ldq_ctx *ctx, const ldq_op *Q, double *lambda_min, double *lambda_max);
 
 /* a3: shifts sigma_l and weights c_l (l = 1..N) with

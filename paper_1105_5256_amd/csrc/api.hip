@@ -34,6 +34,24 @@ hipError_t launch_csr_abs_rowsum(const int32_t *, const double *, int64_t, doubl
 hipError_t launch_to_float(const double *, float *, size_t, hipStream_t);
 hipError_t launch_jp_round(const int32_t *, const int32_t *, int64_t, int, const int32_t *, int32_t *,
                            unsigned long long *, unsigned long long *, int *, int *, hipStream_t);
+// passcsr.hip
+struct CsrSrc {
+  const int32_t *rowptr, *colind;
+  const double *val;
+  const double *diag;
+};
+struct CsrSrcs {
+  int nsrc;
+  CsrSrc src[1 + LDQ_MAXP];
+};
+hipError_t launch_csr_slice_width(const CsrSrcs &, int64_t, int, int32_t *, hipStream_t);
+hipError_t launch_csr_slab_fill(const CsrSrcs &, int64_t, int, const int64_t *, int32_t *, double *,
+                                double *const *, hipStream_t);
+int csr_register_width(int maxw, int64_t n, int elem);
+template <typename T> hipError_t launch_csr_pass_a(const PassCsr<T> &, int, bool, hipStream_t);
+template <typename T> hipError_t launch_csr_pass_b(const PassCsr<T> &, int, bool, hipStream_t);
+hipError_t launch_csr_tail(const TailArgs &, int, int, int, hipStream_t);
+hipError_t launch_lanczos_check(const double *, const ProbeState *, int, int, double, double, int *, hipStream_t);
 }  // namespace ldq
 
 using namespace ldq;
@@ -109,7 +127,7 @@ struct DevBuf {
 struct ldq_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  DevBuf vec, partials, pstate, sstate, shifts, classes, terms, stats, sums, misc, colbuf, jpkey, jpmask;
+  DevBuf vec, partials, pstate, sstate, shifts, classes, terms, stats, sums, misc, colbuf, jpkey, jpmask, hist;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<double> last_terms;
   int last_nparams = 0;
@@ -142,7 +160,32 @@ struct ldq_op {
   int32_t *rowptr = nullptr, *colind = nullptr;
   double *val = nullptr;
   bool own_csr = false;
+  uint64_t serial = 0;         // identifies the operator in caches keyed by operators
+  double est_lo = 0.0, est_hi = 0.0;   // estimated enclosure of a CSR operator
+  bool est_ok = false;
+  struct Slab *slab = nullptr; // sliced layout of a CSR Q with its derivative operators
 };
+
+// Sliced layout of a CSR operator merged with the patterns of the derivative
+// operators of a call (built on the device, kept until the key changes).
+struct Slab {
+  uint64_t key[1 + LDQ_MAXP] = {};
+  int nkey = 0;
+  int nslices = 0, maxw = 0;
+  int64_t nslots = 0;
+  DevBuf sptr, col, val, gval[LDQ_MAXP];
+  void release() {
+    sptr.release();
+    col.release();
+    val.release();
+    for (auto &g : gval) g.release();
+  }
+};
+
+static uint64_t next_serial() {
+  static uint64_t counter = 0;
+  return __atomic_add_fetch(&counter, 1, __ATOMIC_RELAXED);
+}
 
 static int set_device(ldq_ctx *ctx) {
   HIPCHK(hipSetDevice(ctx->device));
@@ -176,7 +219,7 @@ extern "C" void ldq_destroy(ldq_ctx *c) {
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
   for (DevBuf *b : {&c->vec, &c->partials, &c->pstate, &c->sstate, &c->shifts, &c->classes,
-                    &c->terms, &c->stats, &c->sums, &c->misc, &c->colbuf, &c->jpkey, &c->jpmask})
+                    &c->terms, &c->stats, &c->sums, &c->misc, &c->colbuf, &c->jpkey, &c->jpmask, &c->hist})
     b->release();
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
@@ -241,6 +284,7 @@ extern "C" int ldq_op_lattice(ldq_ctx *c, int ndim, const int64_t *shape, int ki
   if (n > (int64_t)1 << 30) return fail(LDQ_E_INVALID, "lattice too large (%lld sites)", (long long)n);
   CHK(set_device(c));
   ldq_op *op = new ldq_op();
+  op->serial = next_serial();
   op->ctx = c;
   op->kind = OPK_LATTICE;
   op->ndim = ndim;
@@ -270,6 +314,7 @@ extern "C" int ldq_op_diag(ldq_ctx *c, int64_t n, const double *d, unsigned flag
   if (!c || !d || !out || n < 1) return fail(LDQ_E_INVALID, "invalid diagonal operator arguments");
   CHK(set_device(c));
   ldq_op *op = new ldq_op();
+  op->serial = next_serial();
   op->ctx = c;
   op->kind = OPK_DIAG;
   op->n = n;
@@ -300,6 +345,7 @@ extern "C" int ldq_op_csr(ldq_ctx *c, int64_t n, int64_t nnz, const int32_t *row
   }
   CHK(set_device(c));
   ldq_op *op = new ldq_op();
+  op->serial = next_serial();
   op->ctx = c;
   op->kind = OPK_CSR;
   op->n = n;
@@ -394,6 +440,7 @@ extern "C" int ldq_op_obs_gram(ldq_ctx *c, const ldq_op *like, int64_t nobs, con
   if (like->kind != OPK_LATTICE || like->ndim != 2) return fail(LDQ_E_UNSUPPORTED, "needs a 2-D lattice operator");
   CHK(set_device(c));
   ldq_op *op = new ldq_op();
+  op->serial = next_serial();
   op->ctx = c;
   op->kind = OPK_OBSGRAM;
   op->ndim = 2;
@@ -426,6 +473,10 @@ extern "C" void ldq_op_destroy(ldq_op *op) {
     if (op->rowptr) hipFree(op->rowptr);
     if (op->colind) hipFree(op->colind);
     if (op->val) hipFree(op->val);
+  }
+  if (op->slab) {
+    op->slab->release();
+    delete op->slab;
   }
   delete op;
 }
@@ -525,11 +576,17 @@ static int spectrum(const ldq_op *Q, double *lmin, double *lmax) {
   return fail(LDQ_E_UNSUPPORTED, "no automatic enclosure for this operator kind; pass lambda_min/lambda_max");
 }
 
+static int csr_bounds(ldq_ctx *c, ldq_op *Q, double *lo, double *hi);
+
 extern "C" int ldq_spectrum_bounds(ldq_ctx *c, const ldq_op *Q, double *lmin, double *lmax) {
   if (!c || !Q || !lmin || !lmax) return fail(LDQ_E_INVALID, "NULL argument");
+  if (Q->ctx != c) return fail(LDQ_E_INVALID, "operator belongs to another context");
   CHK(set_device(c));
   double lo, hi;
-  CHK(spectrum(Q, &lo, &hi));
+  if (Q->kind == OPK_CSR)
+    CHK(csr_bounds(c, const_cast<ldq_op *>(Q), &lo, &hi));
+  else
+    CHK(spectrum(Q, &lo, &hi));
   *lmin = lo;
   *lmax = hi;
   return LDQ_OK;
@@ -756,7 +813,9 @@ struct Call {
   Colouring col;
   std::vector<int32_t> classes;   // non-empty colour classes (probe -> colour)
   double lmin, lmax;
+  bool estimated;                 // enclosure from the Lanczos estimate (refined when a probe contradicts it)
   int ntiles;
+  int stats[8];
 };
 
 template <typename T>
@@ -783,6 +842,110 @@ static int fill_grad_terms(Call &k, GradTerm<T> *g) {
     }
     g[i] = t;
   }
+  return LDQ_OK;
+}
+
+// Lanczos coefficients kept per probe: all iterations up to 8192, within
+// 64 MiB for the probe block.
+static int hist_cap(int block, int max_iter) {
+  const int64_t budget = ((int64_t)64 << 20) / (16 * (int64_t)std::max(block, 1));
+  return (int)std::max<int64_t>(16, std::min<int64_t>({(int64_t)max_iter + 1, 8192, budget}));
+}
+
+// Interval the Lanczos eigenvalues may leave the enclosure [lo, hi] by through
+// rounding (vectors of element size elem) before the check reports them.
+static void check_interval(double lo, double hi, int elem, double *clo, double *chi) {
+  const double eps = elem == 4 ? 5.96e-8 : 1.11e-16;
+  const double slack = 256.0 * eps * hi;
+  *clo = lo - (1e-3 * lo + slack);
+  *chi = hi + (1e-3 * hi + slack);
+}
+
+// Extreme eigenvalues of the Lanczos matrix of K recorded CG steps (pairs
+// alpha_i, beta_{i-1}), by bisection on Sturm counts.
+static int sturm_below(const double *h, int K, double x) {
+  double d = 1.0, aprev = 1.0;
+  int cnt = 0;
+  for (int i = 0; i < K; ++i) {
+    double diag = 1.0 / h[2 * i], off2 = 0.0;
+    if (i > 0) {
+      diag += h[2 * i + 1] / aprev;
+      off2 = h[2 * i + 1] / (aprev * aprev);
+    }
+    d = (diag - x) - (i > 0 ? off2 / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    cnt += d < 0.0;
+    aprev = h[2 * i];
+  }
+  return cnt;
+}
+
+static void lanczos_extremes(const double *h, int K, double *tmin, double *tmax) {
+  std::vector<double> diag(K), off(K + 1, 0.0);   // off[i] couples rows i - 1 and i
+  for (int i = 0; i < K; ++i) {
+    diag[i] = 1.0 / h[2 * i];
+    if (i > 0) {
+      diag[i] += h[2 * i + 1] / h[2 * (i - 1)];
+      off[i] = std::sqrt(std::max(h[2 * i + 1], 0.0)) / std::fabs(h[2 * (i - 1)]);
+    }
+  }
+  double glo = INFINITY, ghi = -INFINITY;   // Gershgorin interval of T
+  for (int i = 0; i < K; ++i) {
+    glo = std::min(glo, diag[i] - off[i] - off[i + 1]);
+    ghi = std::max(ghi, diag[i] + off[i] + off[i + 1]);
+  }
+  auto bisect = [&](int target) {   // smallest x with at least `target` eigenvalues below it
+    double a = glo, b = ghi;
+    for (int it = 0; it < 200 && b - a > 1e-15 * std::max(std::fabs(a), std::fabs(b)); ++it) {
+      const double mid = 0.5 * (a + b);
+      if (sturm_below(h, K, mid) >= target) b = mid; else a = mid;
+    }
+    return 0.5 * (a + b);
+  };
+  *tmin = bisect(1);
+  *tmax = bisect(K);
+}
+
+// Reduce the per-probe terms in probe order, bring the sums, the statistics
+// and the terms to the host and fill the common fields of info.
+static int collect_results(Call &k, int nprobes_total, double kernel_ms, int64_t passes, ldq_info *info,
+                           double *out_sums, int64_t *iters_total) {
+  ldq_ctx *c = k.c;
+  const int P = k.nparams;
+  HIPCHK(launch_sum_terms(c->terms.as<double>(), nprobes_total, 1 + P, c->sums.as<double>(), c->stream));
+  double sums[1 + LDQ_MAXP];
+  HIPCHK(hipMemcpyAsync(sums, c->sums.ptr, (1 + P) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(k.stats, c->stats.ptr, sizeof k.stats, hipMemcpyDeviceToHost, c->stream));
+  c->last_terms.resize((size_t)nprobes_total * (1 + P));
+  HIPCHK(hipMemcpyAsync(c->last_terms.data(), c->terms.ptr, c->last_terms.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->last_nparams = P;
+  c->last_count = nprobes_total;
+  for (int i = 0; i <= P; ++i) out_sums[i] = sums[i];
+  std::memcpy(iters_total, k.stats + 2, sizeof *iters_total);
+  if (info) {
+    info->ncolours = nprobes_total;
+    info->iters_max = k.stats[1];
+    info->iters_total = *iters_total;
+    info->lambda_min = k.lmin;
+    info->lambda_max = k.lmax;
+    info->loop_seconds = kernel_ms * 1e-3;
+    info->passes = passes;
+    info->probe_passes = *iters_total;
+    uint64_t rbits;
+    std::memcpy(&rbits, k.stats + 6, sizeof rbits);
+    info->max_rel_residual = __builtin_bit_cast(double, rbits);
+    info->enclosure_violations = k.stats[4];
+  }
+  return LDQ_OK;
+}
+
+static int finish_status(const Call &k, bool stalled) {
+  if (stalled) return fail(LDQ_E_NO_CONVERGENCE, "probes did not stop within max_iter");
+  if (k.stats[0] == 2) return fail(LDQ_E_NOT_SPD, "the Krylov recurrence met p^T Q p <= 0 or a non-finite value");
+  if (k.stats[0] == 3)
+    return fail(LDQ_E_NO_CONVERGENCE, "max_iter = %d reached before every shift converged", k.o.max_iter);
   return LDQ_OK;
 }
 
@@ -841,6 +1004,13 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   ta.grad_tol2 = gt * gt;
   ta.max_iter = k.o.max_iter;
   ta.active_count = active_count;
+  ta.need_base = P > 0;
+  const int hcap = hist_cap(block, k.o.max_iter);
+  CHK(c->hist.reserve((size_t)block * hcap * 2 * sizeof(double)));
+  ta.hist = c->hist.as<double>();
+  ta.hist_cap = hcap;
+  double clo, chi;
+  check_interval(k.lmin, k.lmax, (int)sizeof(T), &clo, &chi);
 
   GradTerm<T> grads[LDQ_MAXP] = {};
   CHK(fill_grad_terms<T>(k, grads));
@@ -969,32 +1139,13 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
         break;
       }
     }
+    HIPCHK(launch_lanczos_check(ta.hist, st[1], nb, hcap, clo, chi, c->stats.as<int>(), c->stream));
     HIPCHK(launch_probe_terms(st[1], ta.sh, dcoef, nb, N, P, c->terms.as<double>(), first, c->stats.as<int>(),
                               c->stream));
   }
-  HIPCHK(launch_sum_terms(c->terms.as<double>(), nprobes_total, 1 + P, c->sums.as<double>(), c->stream));
-  double sums[1 + LDQ_MAXP];
-  int stats[4];
-  HIPCHK(hipMemcpyAsync(sums, c->sums.ptr, (1 + P) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(stats, c->stats.ptr, sizeof stats, hipMemcpyDeviceToHost, c->stream));
-  c->last_terms.resize((size_t)nprobes_total * (1 + P));
-  HIPCHK(hipMemcpyAsync(c->last_terms.data(), c->terms.ptr, c->last_terms.size() * sizeof(double),
-                        hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  c->last_nparams = P;
-  c->last_count = nprobes_total;
-  for (int i = 0; i <= P; ++i) out_sums[i] = sums[i];
   int64_t iters_total = 0;
-  std::memcpy(&iters_total, stats + 2, sizeof iters_total);
+  CHK(collect_results(k, nprobes_total, kernel_ms, passes, info, out_sums, &iters_total));
   if (info) {
-    info->ncolours = nprobes_total;
-    info->iters_max = stats[1];
-    info->iters_total = iters_total;
-    info->lambda_min = k.lmin;
-    info->lambda_max = k.lmax;
-    info->loop_seconds = kernel_ms * 1e-3;
-    info->passes = passes;
-    info->probe_passes = iters_total;
     // vectors: first pass writes r, p; every later pass reads and writes both;
     // operator fields (kappa2 / derivative diagonals / observation planes) once per launch
     const double sv = (double)sizeof(T);
@@ -1005,12 +1156,374 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
       if (grads[i].kind == GK_DIAG || (grads[i].kind == GK_SHIFTED && grads[i].field)) fields += 1.0;
     info->bytes_model = sv * (double)n * (4.0 * (double)iters_total - 2.0 * (double)nprobes_total) +
                         sv * (double)n * fields * (double)(passes - 2);
-    info->max_rel_residual = 0.0;
   }
-  if (stalled) return fail(LDQ_E_NO_CONVERGENCE, "probes did not stop within max_iter");
-  if (stats[0] == 2) return fail(LDQ_E_NOT_SPD, "the Krylov recurrence met p^T Q p <= 0 or a non-finite value");
-  if (stats[0] == 3) return fail(LDQ_E_NO_CONVERGENCE, "max_iter = %d reached before every shift converged",
-                                 k.o.max_iter);
+  return finish_status(k, stalled);
+}
+
+// ---------------------------------------------------- general sparse operators
+// Sliced layout of Q merged with the derivative operators of the call (values
+// in FP64 for both precisions: rounding the operator itself to FP32 would
+// perturb Q by its condition number); cached on Q and rebuilt when the
+// derivative operators change.
+static int csr_slab(Call &k, Slab **out) {
+  ldq_ctx *c = k.c;
+  ldq_op *Q = k.Q;
+  const int P = k.nparams;
+  uint64_t key[1 + LDQ_MAXP] = {Q->serial};
+  for (int i = 0; i < P; ++i) key[1 + i] = k.dQ[i]->serial;
+  Slab *sl = Q->slab;
+  if (sl && sl->nkey == 1 + P && std::equal(key, key + 1 + P, sl->key)) {
+    *out = sl;
+    return LDQ_OK;
+  }
+  if (!sl) {
+    sl = new (std::nothrow) Slab();
+    if (!sl) return fail(LDQ_E_NO_MEMORY, "slab descriptor");
+    Q->slab = sl;
+  }
+  sl->nkey = 0;   // invalid until complete
+  const int64_t n = Q->n;
+  const int64_t nsl = (n + 63) / 64;
+  if (nsl > INT32_MAX / 4) return fail(LDQ_E_UNSUPPORTED, "operator too large");
+  const int nslices = (int)nsl;
+  CsrSrcs S{};
+  S.nsrc = 1 + P;
+  S.src[0] = CsrSrc{Q->rowptr, Q->colind, Q->val, nullptr};
+  for (int i = 0; i < P; ++i) {
+    const ldq_op *d = k.dQ[i];
+    if (d->kind == OPK_CSR)
+      S.src[1 + i] = CsrSrc{d->rowptr, d->colind, d->val, nullptr};
+    else
+      S.src[1 + i] = CsrSrc{nullptr, nullptr, nullptr, d->field};
+  }
+  DevBuf wbuf;
+  CHK(wbuf.reserve((size_t)nslices * sizeof(int32_t)));
+  HIPCHK(launch_csr_slice_width(S, n, nslices, wbuf.as<int32_t>(), c->stream));
+  std::vector<int32_t> w(nslices);
+  HIPCHK(hipMemcpyAsync(w.data(), wbuf.ptr, (size_t)nslices * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::vector<int64_t> sp(nslices + 1);
+  sp[0] = 0;
+  int maxw = 0;
+  for (int i = 0; i < nslices; ++i) {
+    maxw = std::max(maxw, (int)w[i]);
+    sp[i + 1] = sp[i] + 64 * (int64_t)w[i];
+  }
+  const int64_t nslots = std::max<int64_t>(sp[nslices], 64);
+  if (nslots >= ((int64_t)1 << 40)) return fail(LDQ_E_UNSUPPORTED, "operator too large");
+  CHK(sl->sptr.reserve((size_t)(nslices + 1) * sizeof(int64_t)));
+  CHK(sl->col.reserve((size_t)nslots * sizeof(int32_t)));
+  CHK(sl->val.reserve((size_t)nslots * sizeof(double)));
+  double *g[LDQ_MAXP] = {};
+  for (int i = 0; i < P; ++i) {
+    CHK(sl->gval[i].reserve((size_t)nslots * sizeof(double)));
+    g[i] = sl->gval[i].as<double>();
+  }
+  HIPCHK(hipMemcpyAsync(sl->sptr.ptr, sp.data(), sp.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_csr_slab_fill(S, n, nslices, sl->sptr.as<int64_t>(), sl->col.as<int32_t>(), sl->val.as<double>(), g,
+                              c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  wbuf.release();
+  sl->nslices = nslices;
+  sl->maxw = maxw;
+  sl->nslots = sp[nslices];
+  std::copy(key, key + 1 + P, sl->key);
+  sl->nkey = 1 + P;
+  *out = sl;
+  return LDQ_OK;
+}
+
+// One probe of all ones through the CSR passes with no shifts: its CG
+// coefficients give the Lanczos matrix whose extreme eigenvalues approximate
+// those of Q from inside.  The upper end of the enclosure is the Gershgorin
+// bound of Q; the lower end is half the smallest Lanczos eigenvalue (refined
+// later if a probe's own Lanczos matrix reaches below it).
+template <typename T>
+static int csr_estimate(Call &k, Slab *sl, double *lo, double *hi) {
+  ldq_ctx *c = k.c;
+  ldq_op *Q = k.Q;
+  const int64_t n = Q->n;
+  const int L = 200;
+  const int W = csr_register_width(sl->maxw, n, (int)sizeof(T));
+  DevBuf zcol, cls, vec, part, pst, hist, rs;
+  CHK(zcol.reserve(n * sizeof(int32_t)));
+  CHK(cls.reserve(sizeof(int32_t)));
+  CHK(vec.reserve(4 * n * sizeof(T)));
+  CHK(part.reserve((size_t)sl->nslices * LDQ_NQ_BASE * sizeof(double)));
+  CHK(pst.reserve(sizeof(ProbeState)));
+  CHK(hist.reserve((size_t)(L + 2) * 2 * sizeof(double)));
+  CHK(rs.reserve(n * sizeof(double)));
+  // misc also serves device_minmax below: size it for that first, so that the
+  // counter taken from it now is not reallocated under the queued launches
+  CHK(c->misc.reserve(512 * sizeof(double)));
+  HIPCHK(hipMemsetAsync(zcol.ptr, 0, n * sizeof(int32_t), c->stream));
+  HIPCHK(hipMemsetAsync(cls.ptr, 0, sizeof(int32_t), c->stream));
+  int *active = c->misc.as<int>();
+  ProbeState *st = pst.as<ProbeState>();
+  TailArgs ta{};
+  ta.part_in = part.as<double>();
+  ta.part_out = part.as<double>();
+  ta.st_in = st;
+  ta.st_out = st;
+  ta.ngrad = 0;
+  ta.nshifts = 0;
+  ta.grad_tol2 = 1e-20;
+  ta.max_iter = L;
+  ta.active_count = active;
+  ta.need_base = 1;
+  ta.hist = hist.as<double>();
+  ta.hist_cap = L + 2;
+  PassCsr<T> a{};
+  a.n = n;
+  a.nslices = sl->nslices;
+  a.nprobes = 1;
+  a.ngrad = 0;
+  a.nq = LDQ_NQ_BASE;
+  a.sptr = sl->sptr.as<int64_t>();
+  a.col = sl->col.as<int32_t>();
+  a.val = sl->val.as<double>();
+  a.colours = zcol.as<int32_t>();
+  a.st = st;
+  a.part = part.as<double>();
+  T *v = vec.as<T>();
+  T *ar = v, *ap = v + n, *br = v + 2 * n, *bp = v + 3 * n;
+  HIPCHK(launch_init_probes(st, 1, cls.as<int32_t>(), active, c->stream));
+  HIPCHK(launch_csr_pass_b<T>(a, W, true, c->stream));
+  HIPCHK(launch_csr_tail(ta, 1, a.nslices, MODE_FIRST, c->stream));
+  a.r_out = ar;
+  a.p_out = ap;
+  HIPCHK(launch_csr_pass_a<T>(a, W, true, c->stream));
+  a.r_in = ar;
+  HIPCHK(launch_csr_pass_b<T>(a, W, false, c->stream));
+  bool in_a = true;
+  for (int it = 0; it < L + 1; ++it) {
+    HIPCHK(launch_csr_tail(ta, 1, a.nslices, MODE_STEP, c->stream));
+    a.r_in = in_a ? ar : br;
+    a.p_in = in_a ? ap : bp;
+    a.r_out = in_a ? br : ar;
+    a.p_out = in_a ? bp : ap;
+    HIPCHK(launch_csr_pass_a<T>(a, W, false, c->stream));
+    a.r_in = a.r_out;
+    HIPCHK(launch_csr_pass_b<T>(a, W, false, c->stream));
+    in_a = !in_a;
+  }
+  // Gershgorin bound of Q
+  HIPCHK(launch_csr_abs_rowsum(Q->rowptr, Q->val, n, rs.as<double>(), c->stream));
+  double glo, ghi;
+  CHK(device_minmax(c, rs.as<double>(), n, &glo, &ghi));
+  ProbeState hs;
+  std::vector<double> h(2 * (size_t)(L + 2));
+  HIPCHK(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(h.data(), hist.ptr, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (hs.status == 2) return fail(LDQ_E_NOT_SPD, "the Krylov recurrence met p^T Q p <= 0 or a non-finite value");
+  const int K = std::min(hs.active ? hs.iter + 1 : hs.iter, L + 2);
+  if (K < 1) return fail(LDQ_E_ENCLOSURE, "the enclosure estimate made no progress");
+  double tmin, tmax;
+  lanczos_extremes(h.data(), K, &tmin, &tmax);
+  if (!(tmin > 0.0) || !std::isfinite(tmax)) return fail(LDQ_E_NOT_SPD, "Lanczos estimate of lambda_min is %g", tmin);
+  *lo = 0.5 * tmin;
+  *hi = std::max(ghi, tmax);
+  return LDQ_OK;
+}
+
+template <typename T>
+static int run_krylov_csr(Call &k, ldq_info *info, double *out_sums) {
+  ldq_ctx *c = k.c;
+  ldq_op *Q = k.Q;
+  const int64_t n = Q->n;
+  const int N = k.o.nshifts;
+  const int P = k.nparams;
+  const int nq = LDQ_NQ_BASE + P;
+  const int nprobes_total = (int)k.classes.size();
+  const int block = (k.o.probe_block > 0) ? std::min(k.o.probe_block, nprobes_total) : nprobes_total;
+  Slab *sl = nullptr;
+  CHK(csr_slab(k, &sl));
+  if (!(k.lmin > 0.0)) {
+    CHK(csr_estimate<T>(k, sl, &k.lmin, &k.lmax));
+    k.estimated = true;
+  }
+  const int W = csr_register_width(sl->maxw, n, (int)sizeof(T));
+  const int ntiles = sl->nslices;
+  const int hcap = hist_cap(block, k.o.max_iter);
+  CHK(c->vec.reserve(4 * (size_t)block * n * sizeof(T)));
+  CHK(c->partials.reserve((size_t)block * ntiles * nq * sizeof(double)));
+  CHK(c->pstate.reserve((size_t)block * sizeof(ProbeState)));
+  CHK(c->sstate.reserve((size_t)block * N * sizeof(ShiftState)));
+  CHK(c->classes.reserve((size_t)nprobes_total * sizeof(int32_t) + 64));
+  CHK(c->terms.reserve((size_t)nprobes_total * (1 + P) * sizeof(double) + 64));
+  CHK(c->stats.reserve(8 * sizeof(int)));
+  CHK(c->sums.reserve(8 * sizeof(double)));
+  CHK(c->shifts.reserve(2 * LDQ_MAXN * sizeof(cplx)));
+  CHK(c->misc.reserve(8 * sizeof(int)));
+  CHK(c->hist.reserve((size_t)block * hcap * 2 * sizeof(double)));
+  T *vec = c->vec.as<T>();
+  T *bufA_r = vec, *bufA_p = vec + (size_t)block * n, *bufB_r = vec + 2 * (size_t)block * n,
+    *bufB_p = vec + 3 * (size_t)block * n;
+  cplx *dsig = c->shifts.as<cplx>(), *dcoef = dsig + LDQ_MAXN;
+  HIPCHK(hipMemcpyAsync(c->classes.ptr, k.classes.data(), nprobes_total * sizeof(int32_t), hipMemcpyHostToDevice,
+                        c->stream));
+  int *active_count = c->misc.as<int>();
+  ProbeState *st = c->pstate.as<ProbeState>();
+  double *part = c->partials.as<double>();
+
+  TailArgs ta{};
+  ta.sh = c->sstate.as<ShiftState>();
+  ta.sigma = dsig;
+  ta.nshifts = N;
+  ta.ngrad = P;
+  ta.tol2 = k.o.tol * k.o.tol;
+  const double gt = k.o.grad_tol > 0.0 ? k.o.grad_tol : k.o.tol;
+  ta.grad_tol2 = gt * gt;
+  ta.max_iter = k.o.max_iter;
+  ta.active_count = active_count;
+  ta.part_in = part;
+  ta.part_out = part;
+  ta.st_in = st;
+  ta.st_out = st;
+  ta.need_base = P > 0;
+  ta.hist = c->hist.as<double>();
+  ta.hist_cap = hcap;
+
+  PassCsr<T> a{};
+  a.n = n;
+  a.nslices = ntiles;
+  a.ngrad = P;
+  a.nq = nq;
+  a.sptr = sl->sptr.as<int64_t>();
+  a.col = sl->col.as<int32_t>();
+  a.val = sl->val.as<double>();
+  for (int i = 0; i < P; ++i) a.gval[i] = sl->gval[i].as<double>();
+  a.colours = k.col.colours;
+  a.st = st;
+  a.part = part;
+
+  const int check = k.o.check_every > 0 ? k.o.check_every : 16;
+  int64_t passes = 0;
+  bool stalled = false;
+  double kernel_ms = 0.0;
+  for (int attempt = 0;; ++attempt) {
+    double clo, chi;
+    check_interval(k.lmin, k.lmax, (int)sizeof(T), &clo, &chi);
+    HIPCHK(launch_shifts(k.lmin, k.lmax, N, dsig, dcoef, c->stream));
+    HIPCHK(hipMemsetAsync(c->stats.ptr, 0, 8 * sizeof(int), c->stream));
+    passes = 0;
+    stalled = false;
+    kernel_ms = 0.0;
+    bool refine = false;
+    for (int first = 0; first < nprobes_total && !refine; first += block) {
+      const int nb = std::min(block, nprobes_total - first);
+      a.nprobes = nb;
+      HIPCHK(launch_init_probes(st, nb, c->classes.as<int32_t>() + first, active_count, c->stream));
+      HIPCHK(hipEventRecord(c->ev0, c->stream));
+      // INIT: dots of v; FIRST: alpha_0, shifts; pass A from v; pass B
+      a.r_in = a.p_in = nullptr;
+      HIPCHK(launch_csr_pass_b<T>(a, W, true, c->stream));
+      HIPCHK(launch_csr_tail(ta, nb, ntiles, MODE_FIRST, c->stream));
+      a.r_out = bufA_r;
+      a.p_out = bufA_p;
+      HIPCHK(launch_csr_pass_a<T>(a, W, true, c->stream));
+      a.r_in = bufA_r;
+      HIPCHK(launch_csr_pass_b<T>(a, W, false, c->stream));
+      passes += 1;
+      bool in_a = true;
+      int h_active = nb;
+      int64_t steps = 0;
+      bool chunk_open = true;
+      while (h_active > 0) {
+        if (!chunk_open) HIPCHK(hipEventRecord(c->ev0, c->stream));
+        for (int i = 0; i < check; ++i) {
+          HIPCHK(launch_csr_tail(ta, nb, ntiles, MODE_STEP, c->stream));
+          a.r_in = in_a ? bufA_r : bufB_r;
+          a.p_in = in_a ? bufA_p : bufB_p;
+          a.r_out = in_a ? bufB_r : bufA_r;
+          a.p_out = in_a ? bufB_p : bufA_p;
+          HIPCHK(launch_csr_pass_a<T>(a, W, false, c->stream));
+          a.r_in = a.r_out;
+          HIPCHK(launch_csr_pass_b<T>(a, W, false, c->stream));
+          in_a = !in_a;
+        }
+        HIPCHK(hipEventRecord(c->ev1, c->stream));
+        chunk_open = false;
+        passes += check;
+        steps += check;
+        HIPCHK(hipMemcpyAsync(&h_active, active_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        kernel_ms += ms;
+        if (steps > (int64_t)k.o.max_iter + 2 * check) {
+          stalled = true;
+          break;
+        }
+      }
+      HIPCHK(launch_lanczos_check(ta.hist, st, nb, hcap, clo, chi, c->stats.as<int>(), c->stream));
+      if (k.estimated && attempt < 3) {
+        int viol = 0;
+        HIPCHK(hipMemcpyAsync(&viol, c->stats.as<int>() + 4, sizeof viol, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (viol > 0) {
+          // a probe saw an eigenvalue below the estimated lower end: move
+          // the lower end to half the smallest Lanczos eigenvalue seen
+          std::vector<ProbeState> hs(nb);
+          std::vector<double> h((size_t)nb * hcap * 2);
+          HIPCHK(hipMemcpyAsync(hs.data(), st, nb * sizeof(ProbeState), hipMemcpyDeviceToHost, c->stream));
+          HIPCHK(hipMemcpyAsync(h.data(), ta.hist, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+          HIPCHK(hipStreamSynchronize(c->stream));
+          double tmin = k.lmin, tmax = k.lmax;
+          for (int j = 0; j < nb; ++j) {
+            const int K = std::min(hs[j].active ? hs[j].iter + 1 : hs[j].iter, hcap);
+            if (K < 1) continue;
+            double a0, a1;
+            lanczos_extremes(h.data() + (size_t)j * hcap * 2, K, &a0, &a1);
+            tmin = std::min(tmin, a0);
+            tmax = std::max(tmax, a1);
+          }
+          if (!(tmin > 0.0)) return fail(LDQ_E_NOT_SPD, "a probe's Lanczos matrix has eigenvalue %g", tmin);
+          k.lmin = 0.5 * tmin;
+          k.lmax = std::max(k.lmax, tmax);
+          refine = true;
+          break;
+        }
+      }
+      HIPCHK(launch_probe_terms(st, ta.sh, dcoef, nb, N, P, c->terms.as<double>(), first, c->stats.as<int>(),
+                                c->stream));
+    }
+    if (!refine) break;
+  }
+  if (k.estimated) {
+    Q->est_lo = k.lmin;
+    Q->est_hi = k.lmax;
+    Q->est_ok = true;
+  }
+  int64_t iters_total = 0;
+  CHK(collect_results(k, nprobes_total, kernel_ms, passes, info, out_sums, &iters_total));
+  if (info) {
+    // per probe and iteration: pass A reads r, p and writes r, p, pass B
+    // reads r (the first pass A writes only); per iteration the slab once in
+    // each pass and the colour array once in each pass
+    const double sv = (double)sizeof(T);
+    const double slots = (double)sl->nslots, idx = 8.0 * (sl->nslices + 1);
+    const double slab_a = slots * (4.0 + 8.0 * (1.0 + P)) + idx, slab_b = slots * 12.0 + idx;
+    info->bytes_model = sv * (double)n * (5.0 * (double)iters_total - 2.0 * (double)nprobes_total) +
+                        (slab_a + slab_b + 8.0 * (double)n) * (double)passes + slab_b + 4.0 * (double)n;
+  }
+  return finish_status(k, stalled);
+}
+
+static int csr_bounds(ldq_ctx *c, ldq_op *Q, double *lo, double *hi) {
+  if (!Q->est_ok) {
+    Call k{};
+    k.c = c;
+    k.Q = Q;
+    ldq_options_default(&k.o);
+    Slab *sl = nullptr;
+    CHK(csr_slab(k, &sl));
+    CHK(csr_estimate<double>(k, sl, &Q->est_lo, &Q->est_hi));
+    Q->est_ok = true;
+  }
+  *lo = Q->est_lo;
+  *hi = Q->est_hi;
   return LDQ_OK;
 }
 
@@ -1031,18 +1544,20 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
   if (!(k.o.tol > 0.0) || !(k.o.grad_tol >= 0.0) || k.o.max_iter < 1)
     return fail(LDQ_E_INVALID, "tol must be > 0, grad_tol >= 0, max_iter >= 1");
   if (k.o.precision != LDQ_FP64 && k.o.precision != LDQ_MIXED) return fail(LDQ_E_INVALID, "unknown precision");
-  if (Q->kind != OPK_LATTICE)
-    return fail(LDQ_E_UNSUPPORTED, "the Krylov passes are implemented for lattice operators");
+  if (Q->kind != OPK_LATTICE && Q->kind != OPK_CSR)
+    return fail(LDQ_E_UNSUPPORTED, "the Krylov passes are implemented for lattice and CSR operators");
   if (Q->kind == OPK_LATTICE && Q->ndim == 2 && nparams > 2)
     return fail(LDQ_E_UNSUPPORTED, "at most 2 derivative operators on 2-D lattices");
   for (int i = 0; i < nparams; ++i) {
     if (!dQ[i]) return fail(LDQ_E_INVALID, "dQ[%d] is NULL", i);
     if (dQ[i]->n != Q->n) return fail(LDQ_E_INVALID, "dQ[%d] has %lld rows, Q has %lld", i, (long long)dQ[i]->n,
                                       (long long)Q->n);
+    if (Q->kind == OPK_CSR && dQ[i]->kind != OPK_CSR && dQ[i]->kind != OPK_DIAG)
+      return fail(LDQ_E_UNSUPPORTED, "derivatives of a CSR operator must be CSR or diagonal operators");
     if (dQ[i]->kind == OPK_LATTICE && (dQ[i]->ndim != Q->ndim || dQ[i]->shape[0] != Q->shape[0] ||
                                        dQ[i]->shape[1] != Q->shape[1] || dQ[i]->shape[2] != Q->shape[2]))
       return fail(LDQ_E_INVALID, "dQ[%d] is on another lattice", i);
-    if (dQ[i]->kind == OPK_OBSGRAM && (Q->ndim != 2 || !Q->obs9))
+    if (dQ[i]->kind == OPK_OBSGRAM && (Q->kind != OPK_LATTICE || Q->ndim != 2 || !Q->obs9))
       return fail(LDQ_E_UNSUPPORTED, "an observation-gram derivative needs a 2-D Q with an observation term");
     k.dQ[i] = const_cast<ldq_op *>(dQ[i]);
   }
@@ -1075,6 +1590,11 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
     k.lmin = k.o.lambda_min;
     k.lmax = k.o.lambda_max;
     if (!(k.lmax >= k.lmin)) return fail(LDQ_E_ENCLOSURE, "lambda_max < lambda_min");
+  } else if (Q->kind == OPK_CSR) {
+    // estimated by the Krylov driver (Lanczos), or the operator's last estimate
+    k.lmin = Q->est_ok ? Q->est_lo : 0.0;
+    k.lmax = Q->est_ok ? Q->est_hi : 0.0;
+    k.estimated = true;
   } else {
     CHK(spectrum(Q, &k.lmin, &k.lmax));
   }
@@ -1088,7 +1608,11 @@ static int logdet_impl(ldq_ctx *c, const ldq_op *Q, int nparams, const ldq_op *c
   CHK(prepare_call(k, c, Q, nparams, dQ, opts));
   double sums[1 + LDQ_MAXP] = {};
   ldq_info tmp{};
-  int st = (k.o.precision == LDQ_MIXED) ? run_krylov<float>(k, &tmp, sums) : run_krylov<double>(k, &tmp, sums);
+  int st;
+  if (k.Q->kind == OPK_CSR)
+    st = (k.o.precision == LDQ_MIXED) ? run_krylov_csr<float>(k, &tmp, sums) : run_krylov_csr<double>(k, &tmp, sums);
+  else
+    st = (k.o.precision == LDQ_MIXED) ? run_krylov<float>(k, &tmp, sums) : run_krylov<double>(k, &tmp, sums);
   if (st != LDQ_OK && st != LDQ_E_NO_CONVERGENCE) return st;
   if (logdet) *logdet = sums[0];
   if (grad)

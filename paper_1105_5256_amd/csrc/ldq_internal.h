@@ -88,6 +88,9 @@ struct TailArgs {
   double grad_tol2;        // grad_tol^2
   int max_iter;
   int *active_count;       // probes still iterating (decremented once per finished probe)
+  int need_base;           // the base system must reach grad_tol (gradients, enclosure estimate)
+  int hist_cap;            // Lanczos coefficients kept per probe (0: none)
+  double *hist;            // [probe][hist_cap][2]: (alpha_i, beta_{i-1}) of iteration i
 };
 
 enum PassMode { MODE_INIT = 0, MODE_FIRST = 1, MODE_STEP = 2 };
@@ -132,6 +135,32 @@ struct Pass3D {
   T *r_out, *p_out;
   int mode;
   TailArgs tail;
+};
+
+// General sparse operator.  The rows are cut into slices of 64 (one wave
+// each); slice s stores its entries column-major, entry k of row 64 s + l at
+// sptr[s] + 64 k + l, for k below the slice width (sptr[s+1] - sptr[s]) / 64.
+// The pattern is the union of the patterns of Q and of the derivative
+// operators, so val and gval[i] share the slots (zero where an operator has
+// no entry).  One iteration is pass A (p_k formed on the fly, r_{k+1} =
+// r_k - alpha_k Q p_k, dots gamma', rho', omega_i), pass B (delta' =
+// r_{k+1}^T Q r_{k+1}) and the per-probe tail launch.
+template <typename T>
+struct PassCsr {
+  int64_t n;
+  int nslices;                  // also the tiles of the partials
+  int nprobes;
+  int ngrad;
+  int nq;
+  const int64_t *sptr;
+  const int32_t *col;
+  const double *val;            // operator values stay FP64 in both precisions
+  const double *gval[LDQ_MAXP];
+  const int32_t *colours;
+  const ProbeState *st;
+  const T *r_in, *p_in;
+  T *r_out, *p_out;
+  double *part;                 // [probe][nq][slice]
 };
 
 }  // namespace ldq

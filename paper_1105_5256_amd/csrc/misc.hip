@@ -38,10 +38,54 @@ __global__ void probe_terms_kernel(const ProbeState *st, const ShiftState *sh, c
   double *dst = terms + (size_t)(first + j) * (1 + ngrad);
   dst[0] = t;
   for (int i = 0; i < ngrad; ++i) dst[1 + i] = st[j].grad[i];
-  // stats: [0] worst status, [1] max iterations, [2..3] total iterations (64-bit)
+  // stats: [0] worst status, [1] max iterations, [2..3] total iterations
+  // (64-bit), [6..7] max final ||r|| / ||v|| (a non-negative double: its bit
+  // pattern orders like the value)
   atomicMax(stats + 0, st[j].status);
   atomicMax(stats + 1, st[j].iter);
   atomicAdd((unsigned long long *)(stats + 2), (unsigned long long)st[j].iter);
+  const double res = st[j].vnorm2 > 0.0 ? sqrt(fmax(st[j].gamma, 0.0) / st[j].vnorm2) : 0.0;
+  atomicMax((unsigned long long *)(stats + 6), (unsigned long long)__double_as_longlong(res));
+}
+
+// Enclosure check: the CG coefficients of a probe define its Lanczos
+// tridiagonal matrix T (diagonal 1/alpha_i + beta_{i-1}/alpha_{i-1},
+// off-diagonal squared beta_{i-1}/alpha_{i-1}^2), whose eigenvalues lie in the
+// spectrum of Q up to rounding.  Sturm sequences (LDL^T pivots of T - lo I and
+// hi I - T) count its eigenvalues below lo and above hi; stats[4] receives the
+// number of probes with any.
+__global__ void lanczos_check_kernel(const double *hist, const ProbeState *st, int nprobes, int cap, double lo,
+                                     double hi, int *stats) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nprobes) return;
+  const int K = min(st[j].active ? st[j].iter + 1 : st[j].iter, cap);
+  const double *h = hist + (size_t)j * cap * 2;
+  double dl = 1.0, dh = 1.0, aprev = 1.0;
+  int below = 0, above = 0;
+  for (int i = 0; i < K; ++i) {
+    const double al = h[2 * i], be = h[2 * i + 1];
+    double diag = 1.0 / al, off2 = 0.0;
+    if (i > 0) {
+      diag += be / aprev;
+      off2 = be / (aprev * aprev);
+    }
+    dl = (diag - lo) - (i > 0 ? off2 / dl : 0.0);
+    dh = (hi - diag) - (i > 0 ? off2 / dh : 0.0);
+    if (dl == 0.0) dl = -1e-300;
+    if (dh == 0.0) dh = -1e-300;
+    below += dl < 0.0;
+    above += dh < 0.0;
+    aprev = al;
+  }
+  if (below + above > 0) atomicAdd(stats + 4, 1);
+}
+
+hipError_t launch_lanczos_check(const double *hist, const ProbeState *st, int nprobes, int cap, double lo, double hi,
+                                int *stats, hipStream_t s) {
+  if (cap <= 0 || nprobes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lanczos_check_kernel, dim3((nprobes + 255) / 256), dim3(256), 0, s, hist, st, nprobes, cap, lo,
+                     hi, stats);
+  return hipGetLastError();
 }
 
 hipError_t launch_probe_terms(const ProbeState *st, const ShiftState *sh, const cplx *coef, int nprobes,

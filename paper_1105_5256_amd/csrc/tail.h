@@ -189,7 +189,7 @@ __device__ inline Step pass_prologue(const TailArgs &ta, int probe, int tile, in
         if (i < ta.ngrad) ps.grad[i] += ak * tot[LDQ_NQ_BASE + i];   // w.x_{k+1} = w.x_k + alpha_k w.p_k
     }
     ps.iter += 1;
-    const bool base_ok = (ta.ngrad == 0) || (gn <= ta.grad_tol2 * ps.vnorm2);
+    const bool base_ok = !ta.need_base || (gn <= ta.grad_tol2 * ps.vnorm2);
     if (!done) {
       if (gn == 0.0 || (all_frozen && base_ok)) {
         done = true;
@@ -218,6 +218,13 @@ __device__ inline Step pass_prologue(const TailArgs &ta, int probe, int tile, in
       ps.active = 0;
       ps.status = status;
       atomicSub(ta.active_count, 1);
+    } else if (ps.iter < ta.hist_cap) {
+      // the CG coefficients define the Lanczos tridiagonal matrix of the probe
+      // (diagonal 1/alpha_i + beta_{i-1}/alpha_{i-1}, off-diagonal
+      // sqrt(beta_{i-1})/alpha_{i-1}); its eigenvalues lie in the spectrum of Q
+      double *h = ta.hist + ((size_t)probe * ta.hist_cap + ps.iter) * 2;
+      h[0] = ps.alpha;
+      h[1] = mode == MODE_FIRST ? 0.0 : ps.beta_prev;
     }
     ta.st_out[probe] = ps;
   }

@@ -55,6 +55,7 @@ class ldq_info(ctypes.Structure):
         ("passes", ctypes.c_int64),
         ("probe_passes", ctypes.c_int64),
         ("bytes_model", ctypes.c_double),
+        ("enclosure_violations", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -19,7 +19,12 @@ are synthetic stand-ins with the same operators and scales:
 * ``posterior2d``     Q_p = (kappa2 I + L)^2 + tau A^T A with A the bilinear
                       interpolation at uniformly scattered points;
 * ``batch2d``         many independent square fields of uneven size and
-                      kappa2 ~ LogUniform(0.01, 1).
+                      kappa2 ~ LogUniform(0.01, 1);
+* ``lattice2d_sq_csr`` the 13-point operator written out as a CSR matrix (the
+                      "CSR form" of the 512 x 512 workload);
+* ``random_spd_csr``  a seeded sparse SPD matrix on a random graph of uneven
+                      degree (weighted graph Laplacian plus a positive
+                      diagonal), for the general sparse path.
 """
 import numpy as np
 
@@ -101,6 +106,90 @@ def batch2d(nfields=256, side_lo=32, side_hi=256, seed=5, k=4):
     fields = [dict(kind="sq", shape=(int(s), int(s)), kappa2=float(c), power=2, k=int(k))
               for s, c in zip(sides, kappa2)]
     return dict(kind="batch", fields=fields)
+
+
+def lattice2d_sq_csr(mx, my=None, kappa2=0.05, scale=1.0):
+    """CSR arrays (rowptr, colind, val) of scale * (kappa2 I + L)^2 on an
+    mx x my Dirichlet lattice, site index x + mx y, columns ascending.
+
+    Entries of the product M M with M = kappa2 I + L: (kappa2 + 4)^2 plus the
+    number of in-lattice axis neighbours on the diagonal, -2 (kappa2 + 4) to the
+    axis neighbours, +2 to the diagonal neighbours, +1 two steps along an axis.
+    """
+    my = mx if my is None else my
+    c4 = kappa2 + 4.0
+    x, y = np.meshgrid(np.arange(mx), np.arange(my), indexing="xy")
+    x, y = x.ravel(), y.ravel()
+    deg = (x > 0).astype(np.int64) + (x < mx - 1) + (y > 0) + (y < my - 1)
+    rows, cols, vals = [], [], []
+    offsets = [(0, 0, None), (1, 0, -2 * c4), (-1, 0, -2 * c4), (0, 1, -2 * c4), (0, -1, -2 * c4),
+               (1, 1, 2.0), (1, -1, 2.0), (-1, 1, 2.0), (-1, -1, 2.0),
+               (2, 0, 1.0), (-2, 0, 1.0), (0, 2, 1.0), (0, -2, 1.0)]
+    site = x + mx * y
+    for dx, dy, v in offsets:
+        xx, yy = x + dx, y + dy
+        ok = (xx >= 0) & (xx < mx) & (yy >= 0) & (yy < my)
+        rows.append(site[ok])
+        cols.append((xx + mx * yy)[ok])
+        vals.append((c4 * c4 + deg[ok]) if v is None else np.full(int(ok.sum()), v))
+    return _to_csr(mx * my, np.concatenate(rows), np.concatenate(cols), scale * np.concatenate(vals))
+
+
+def lattice2d_5pt_csr(mx, my=None, kappa2=0.05, scale=1.0):
+    """CSR arrays of scale * (kappa2 I + L) (5-point, Dirichlet) on an mx x my
+    lattice, site index x + mx y: kappa2 + 4 on the diagonal, -1 to the axis
+    neighbours inside the lattice."""
+    my = mx if my is None else my
+    x, y = np.meshgrid(np.arange(mx), np.arange(my), indexing="xy")
+    x, y = x.ravel(), y.ravel()
+    site = x + mx * y
+    rows, cols, vals = [site], [site], [np.full(mx * my, kappa2 + 4.0)]
+    for dx, dy in [(1, 0), (-1, 0), (0, 1), (0, -1)]:
+        xx, yy = x + dx, y + dy
+        ok = (xx >= 0) & (xx < mx) & (yy >= 0) & (yy < my)
+        rows.append(site[ok])
+        cols.append((xx + mx * yy)[ok])
+        vals.append(np.full(int(ok.sum()), -1.0))
+    return _to_csr(mx * my, np.concatenate(rows), np.concatenate(cols), scale * np.concatenate(vals))
+
+
+def random_spd_csr(n, deg_lo=2, deg_hi=12, shift=0.05, seed=7, signs=False):
+    """Sparse SPD matrix on a random graph: vertex i draws d_i ~ U{deg_lo..deg_hi}
+    partners uniformly, edges get weights U(0.5, 1.5) and the pattern is
+    symmetrised; Q = D - W + diag(shift * U(0.5, 2)) (weighted graph Laplacian
+    plus a positive diagonal).  With signs=True, Q -> S Q S for random signs S
+    (same spectrum; the all-ones vector then misses the lowest eigenvector).
+    Returns (rowptr, colind, val)."""
+    rng = np.random.default_rng(seed)
+    d = rng.integers(deg_lo, deg_hi + 1, n)
+    src = np.repeat(np.arange(n), d)
+    dst = rng.integers(0, n, src.size)
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    w = rng.uniform(0.5, 1.5, src.size)
+    a, b = np.minimum(src, dst), np.maximum(src, dst)
+    key = a.astype(np.int64) * n + b
+    key, first = np.unique(key, return_index=True)
+    a, b, w = a[first], b[first], w[first]
+    diag = np.zeros(n)
+    np.add.at(diag, a, w)
+    np.add.at(diag, b, w)
+    diag += shift * rng.uniform(0.5, 2.0, n)
+    rows = np.concatenate([a, b, np.arange(n)])
+    cols = np.concatenate([b, a, np.arange(n)])
+    vals = np.concatenate([-w, -w, diag])
+    if signs:
+        s = rng.choice([-1.0, 1.0], n)
+        vals = vals * s[rows] * s[cols]
+    return _to_csr(n, rows, cols, vals)
+
+
+def _to_csr(n, rows, cols, vals):
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rowptr, rows + 1, 1)
+    return np.cumsum(rowptr).astype(np.int32), cols.astype(np.int32), vals.astype(np.float64)
 
 
 def priority(n, seed):
