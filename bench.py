@@ -1,18 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the probing / multi-shift Krylov log det + gradient on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): the 2-D
-512 x 512 lattice with Q = (0.05 I + L)^2 (13-point operator), distance-4
+Default workload (the configuration the headline metric is quoted on): the
+2-D 512 x 512 lattice with Q = (0.05 I + L)^2 (13-point operator), distance-4
 modular colouring (41 probes), N = 20 contour shifts, gradient with respect
 to kappa^2 (dQ/dkappa^2 = 2 (kappa^2 I + L)), mixed form (vectors stored in
 FP32, all arithmetic in FP64), tol 1e-5 per shifted system and 1e-6 for the
 base system.  One step = one full log det + gradient evaluation through the
 C ABI with the operator already resident on the device.
 
+--config selects one of the other workloads (each printed the same way):
+  lattice64_5pt   64 x 64, Q = 0.1 I + L, distance 2 (5 probes), FP64, tol 1e-10
+  field128        128^3, Q = diag(kappa2(s)) + L, log kappa2 = log 0.1 + 0.5 z(s),
+                  distance 6 (70 probes), mixed, gradient w.r.t. (eta0, eta1)
+  posterior1024   1024 x 1024, Q = (0.05 I + L)^2 + 100 A^T A with 100 000
+                  bilinear observations, distance 4 (41 probes), mixed,
+                  gradient w.r.t. (kappa2, tau)
+  batch256        256 fields (kappa2_f I + L)^2, sides U{32..256}, kappa2_f
+                  LogUniform(0.01, 1), distance 4, mixed, one batched call
+
 Printed: one JSON line with the whole-job throughput (evaluations per second),
-the roofline of the dominant kernel (the fused 2-D pass), the plain FP64 form
+the roofline of the dominant kernel, the other forms of the same workload
 timed beside it, the error of the timed result against a tight FP64 run of
-the same library, and the CPU reference timed on a bounded sample.
+the same library, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -27,7 +37,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass2d_lattice512_sq_traffic.json")
 KERNEL_SOURCES = ["paper_1105_5256_amd/csrc/pass2d.hip", "paper_1105_5256_amd/csrc/tail.h",
-                  "paper_1105_5256_amd/csrc/ldq_internal.h"]
+                  "paper_1105_5256_amd/csrc/ldq_internal.h", "paper_1105_5256_amd/csrc/bufio.h"]
+METRIC = "log det Q evals/s + SpMM HBM GB/s at rel. err 1e-4 vs FP64; fwd+grad"
 
 
 def kernel_hash():
@@ -41,52 +52,201 @@ def kernel_hash():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default per workload)")
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="lattice512_sq",
+                    choices=["lattice512_sq", "lattice64_5pt", "field128", "posterior1024", "batch256"])
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU reference timing")
-    ap.add_argument("--no-forms", action="store_true", help="skip the FP64-form, CSR-form and accuracy runs")
+    ap.add_argument("--no-forms", action="store_true", help="skip the other forms and the accuracy runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(wl, iters_total, sample_iters=200):
-    """The CPU oracle (textbook CG-M with per-shift vectors, FP64) on a bounded
-    sample: the first `sample_iters` iterations of probe 0, scaled by the
-    workload's total probe-iterations."""
-    import numpy as np
-    from oracle import colouring, exact, krylov, lattice, shifts
+# ------------------------------------------------------------------ workloads
+class Workload:
+    """Operators of one benchmark configuration on the device, and how to run it."""
 
-    shape, kappa2 = wl["shape"], wl["kappa2"]
-    M = lattice.shifted_laplacian(shape, kappa2)
-    Q = lattice.squared(M)
-    C, co = colouring.find_modular(2, 2 * wl["k"])
-    col = colouring.modular_colouring(shape, C, co)
-    v = (col == 0).astype(np.float64)
-    lo, hi = exact.spectrum_closed_form(shape, kappa2, 2)
-    sig, _ = shifts.log_shifts(lo, hi, 20)
+    def __init__(self, name, ctx):
+        import numpy as np
+
+        from paper_1105_5256_amd import ldq as L
+        from paper_1105_5256_amd import workloads
+        self.name = name
+        self.ctx = ctx
+        self.batched = False
+        h = ctx.handle
+        if name == "lattice512_sq":
+            wl = workloads.lattice2d_sq(512, kappa2=0.05, k=4)
+            self.wl = wl
+            self.Q = ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SQUARED_SHIFTED_LAPLACIAN, wl["kappa2"]))
+            self.dQ = [ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SHIFTED_LAPLACIAN, wl["kappa2"], scale=2.0))]
+            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 4, 1e-5, 1e-6
+            self.describe = ("lattice512_sq: 2-D 512x512 lattice, Q = (0.05 I + L)^2 (13-point), distance-4 "
+                             "modular colouring (41 probes), N=20 shifts, log det + d/dkappa2")
+            self.kernel = "pass2d_fast<float, R=2, no observations, 1 gradient> (fused 2-D pass)"
+            self.n = 512 * 512
+        elif name == "lattice64_5pt":
+            wl = workloads.lattice2d_5pt(64, 0.1, 2)
+            self.wl = wl
+            self.Q = ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SHIFTED_LAPLACIAN, wl["kappa2"]))
+            self.dQ = [ctx.op(L.ldq_op_diag(h, np.ones(64 * 64)))]
+            self.timed, self.k, self.tol, self.gtol = L.LDQ_FP64, 2, 1e-10, 1e-10
+            self.describe = ("lattice64_5pt: 2-D 64x64 lattice, Q = 0.1 I + L (5-point), distance-2 modular "
+                             "colouring (5 probes), N=20 shifts, tol 1e-10, FP64, log det + d/dkappa2")
+            self.kernel = "pass2d<double, R=1, 1 diagonal gradient> (fused 2-D pass)"
+            self.n = 64 * 64
+        elif name == "field128":
+            wl = workloads.lattice3d_field(128, k=6)
+            self.wl = wl
+            self.Q = ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SHIFTED_LAPLACIAN, 0.0,
+                                             kappa2_field=wl["kappa2_field"]))
+            self.dQ = [ctx.op(L.ldq_op_diag(h, d)) for d in wl["dkappa2"]]
+            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 6, 1e-5, 1e-6
+            self.describe = ("field128: 3-D 128^3 lattice, Q = diag(kappa2(s)) + L (7-point), log kappa2 = "
+                             "log 0.1 + 0.5 z(s), distance-6 modular colouring (70 probes), N=20 shifts, "
+                             "log det + d/d(eta0, eta1)")
+            self.kernel = "pass3d<float> (fused 3-D pass, kappa2 field, 2 diagonal gradients)"
+            self.n = 128 ** 3
+        elif name == "posterior1024":
+            wl = workloads.posterior2d(1024)
+            self.wl = wl
+            self.Q = ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SQUARED_SHIFTED_LAPLACIAN, wl["kappa2"]))
+            L.ldq_op_add_obs(self.Q, wl["corner"], wl["weight"], wl["tau"])
+            dk = ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SHIFTED_LAPLACIAN, wl["kappa2"], scale=2.0))
+            dt = ctx.op(L.ldq_op_obs_gram(h, self.Q, wl["corner"], wl["weight"]))
+            self.dQ = [dk, dt]
+            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 4, 1e-5, 1e-6
+            self.describe = ("posterior1024: 2-D 1024x1024 lattice, Q = (0.05 I + L)^2 + 100 A^T A, 100000 "
+                             "bilinear observations, distance-4 modular colouring (41 probes), N=20 shifts, "
+                             "log det + d/d(kappa2, tau)")
+            self.kernel = "pass2d_fast<float, R=2, observation planes, 2 gradients> (fused 2-D pass)"
+            self.n = 1024 * 1024
+        elif name == "batch256":
+            wl = workloads.batch2d(256)
+            self.wl = wl
+            self.batched = True
+            self.Qs, self.dQs = [], []
+            for f in wl["fields"]:
+                self.Qs.append(ctx.op(L.ldq_op_lattice(h, f["shape"], L.LDQ_SQUARED_SHIFTED_LAPLACIAN,
+                                                       f["kappa2"])))
+                self.dQs.append([ctx.op(L.ldq_op_lattice(h, f["shape"], L.LDQ_SHIFTED_LAPLACIAN, f["kappa2"],
+                                                         scale=2.0))])
+            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 4, 1e-5, 1e-6
+            self.describe = ("batch256: 256 independent 2-D fields (kappa2_f I + L)^2, sides U{32..256}, "
+                             "kappa2_f LogUniform(0.01, 1), distance-4 modular colouring (41 probes each), "
+                             "N=20 shifts, log det + d/dkappa2 per field, one batched call")
+            self.kernel = "pass2d_fast<float, R=2, no observations, 1 gradient> (fused 2-D pass)"
+            self.n = sum(f["shape"][0] * f["shape"][1] for f in wl["fields"])
+        else:
+            raise ValueError(name)
+
+    def opts(self, precision, tol, gtol):
+        from paper_1105_5256_amd import ldq
+        return ldq.ldq_options_default(k=self.k, nshifts=20, tol=tol, grad_tol=gtol, precision=precision)
+
+    def run(self, opts):
+        """One evaluation: (values, gradients, list of info dicts)."""
+        from paper_1105_5256_amd import ldq
+        if self.batched:
+            return ldq.ldq_logdet_batched(self.ctx.handle, self.Qs, self.dQs, opts)
+        v, g, info = ldq.ldq_logdet_grad(self.ctx.handle, self.Q, self.dQ, opts)
+        return [v], [g], [info]
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def rel_err(a, b):
+    import numpy as np
+    a, b = np.asarray(a, dtype=float).ravel(), np.asarray(b, dtype=float).ravel()
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+def timed_runs(w, opts, steps):
+    import torch
+    torch.cuda.synchronize()
+    infos = []
     t0 = time.perf_counter()
-    x, X, it = krylov.cg_m(Q, v, sig, tol=1e-30, maxiter=sample_iters)
-    _ = x @ (2 * (M @ v))
-    dt = time.perf_counter() - t0
-    per_iter = dt / it
-    eval_s = per_iter * iters_total
+    for _ in range(steps):
+        v, g, inf = w.run(opts)
+        infos.extend(inf)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, v, g, infos
+
+
+# ------------------------------------------------------------ CPU reference
+def cpu_baseline(w, one_eval, target_s=12.0):
+    """The CPU oracle (textbook CG-M with per-shift vectors, FP64) on a
+    bounded sample of the same workload: CG-M iterations of probe 0 of the
+    (largest) operator, scaled per site-iteration to the workload's
+    probe-site-iterations."""
+    import numpy as np
+    from oracle import colouring, krylov, lattice, shifts
+
+    wl = w.wl
+    if w.name == "batch256":
+        f = max(wl["fields"], key=lambda f: f["shape"][0])
+        shape, M = f["shape"], lattice.shifted_laplacian(f["shape"], f["kappa2"])
+        Q, dQ, radius = lattice.squared(M), 2 * M, 8
+    elif w.name == "field128":
+        shape = wl["shape"]
+        Q = lattice.shifted_laplacian(shape, wl["kappa2_field"])
+        dQ, radius = None, 6
+    elif w.name == "posterior1024":
+        shape = wl["shape"]
+        M = lattice.shifted_laplacian(shape, wl["kappa2"])
+        Q = lattice.posterior_precision(lattice.squared(M), wl["corner"], wl["weight"], wl["tau"])
+        dQ, radius = 2 * M, 8
+    else:
+        shape = wl["shape"]
+        M = lattice.shifted_laplacian(shape, wl["kappa2"])
+        sq = wl["power"] == 2
+        Q, dQ, radius = (lattice.squared(M), 2 * M, 2 * w.k) if sq else (M, None, w.k)
+    Q = Q.tocsr()
+    C, co = colouring.find_modular(len(shape), radius)
+    v = (colouring.modular_colouring(shape, C, co) == 0).astype(np.float64)
+    lo, hi = one_eval[0]["lambda_min"], one_eval[0]["lambda_max"]
+    sig, _ = shifts.log_shifts(lo, hi, 20)
+
+    def sample(iters):
+        t0 = time.perf_counter()
+        x, X, it = krylov.cg_m(Q, v, sig, tol=1e-30, maxiter=iters)
+        if dQ is not None:
+            _ = x @ (dQ @ v)
+        return time.perf_counter() - t0, it
+
+    t_small, it_small = sample(5)
+    iters = int(max(10, min(2000, target_s / max(t_small / max(it_small, 1), 1e-6))))
+    dt, it = sample(iters)
+    per_site_iter = dt / it / Q.shape[0]
+    site_iters = sum(float(i["iters_total"]) * _n_of(w, j) for j, i in enumerate(one_eval))
+    eval_s = per_site_iter * site_iters
     threads = 1
     try:
         import threadpoolctl
-        info = threadpoolctl.threadpool_info()
-        threads = max([i.get("num_threads", 1) for i in info] + [1])
+        threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] + [1])
     except Exception:
         pass
     return {"value": 1.0 / eval_s, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {it} CG-M iterations (20 shifts, per-shift vectors, FP64) of probe 0 of 41 "
-                      f"on the 512x512 13-point lattice, {dt:.1f} s, scaled by the workload's "
-                      f"{iters_total} probe-iterations; scipy sparse products and numpy updates run "
-                      f"single-threaded (BLAS pool {threads} threads, {os.cpu_count()} host cores)"}
+            "sample": f"first {it} CG-M iterations (20 shifts, per-shift vectors, FP64) of probe 0 on the "
+                      f"{'x'.join(map(str, shape))} operator ({Q.shape[0]} sites), {dt:.1f} s, scaled per "
+                      f"site-iteration to the workload's {site_iters:.3g} probe-site-iterations; scipy "
+                      f"sparse products and numpy updates run single-threaded (BLAS pool {threads} "
+                      f"threads, {os.cpu_count()} host cores)"}
 
 
+def _n_of(w, j):
+    if w.batched:
+        s = w.wl["fields"][j]["shape"]
+        return s[0] * s[1]
+    return w.n
+
+
+# ----------------------------------------------------------------- the CSR form
 def csr_forms(ctx, wl, nsteps, ref_val, ref_grad):
-    """The same workload with Q and dQ/dkappa2 given as CSR matrices (the
+    """The 512x512 workload with Q and dQ/dkappa2 given as CSR matrices (the
     general sparse passes), the same colouring and enclosure as the stencil
     form, timed in the mixed and FP64 forms."""
     import torch
@@ -103,8 +263,8 @@ def csr_forms(ctx, wl, nsteps, ref_val, ref_grad):
     rp, ci, v = workloads.lattice2d_5pt_csr(*shape, kappa2=kappa2, scale=2.0)
     dQ = ctx.op(ldq.ldq_op_csr(ctx.handle, n, rp, ci, v))
     res = {}
-    for name, prec, tol, gtol in [("csr_mixed", ldq.LDQ_MIXED, 1e-5, 1e-6), ("csr_fp64", ldq.LDQ_FP64, 1e-5, 1e-6)]:
-        opts = ldq.ldq_options_default(k=wl["k"], nshifts=20, tol=tol, grad_tol=gtol, precision=prec,
+    for name, prec in [("csr_mixed", ldq.LDQ_MIXED), ("csr_fp64", ldq.LDQ_FP64)]:
+        opts = ldq.ldq_options_default(k=wl["k"], nshifts=20, tol=1e-5, grad_tol=1e-6, precision=prec,
                                        colouring=ldq.LDQ_COLOUR_USER, user_colours=col, lambda_min=lo,
                                        lambda_max=hi)
         ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
@@ -122,50 +282,46 @@ def csr_forms(ctx, wl, nsteps, ref_val, ref_grad):
     return res
 
 
+DEFAULT_STEPS = {"lattice512_sq": 10, "lattice64_5pt": 20, "field128": 3, "posterior1024": 3, "batch256": 2}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(on several GPUs the probes would be split between ranks and their terms summed with one all-reduce of a few doubles; this build measures one GPU)",
-              file=sys.stderr)
+              f"(on several GPUs the probes would be split between ranks and their terms summed with one "
+              f"all-reduce of a few doubles; this build measures one GPU)", file=sys.stderr)
         sys.exit(2)
     import torch
 
-    from paper_1105_5256_amd import ldq, workloads
+    from paper_1105_5256_amd import ldq
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    wl = workloads.lattice2d_sq(512, kappa2=0.05, k=4)
-    shape, kappa2 = wl["shape"], wl["kappa2"]
+    steps = args.steps if args.steps is not None else DEFAULT_STEPS[args.config]
     ctx = ldq.Context(0)
-    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, kappa2))
-    dQ = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, kappa2, scale=2.0))
-    mixed = ldq.ldq_options_default(k=4, nshifts=20, tol=1e-5, grad_tol=1e-6, precision=ldq.LDQ_MIXED)
-
+    w = Workload(args.config, ctx)
+    progress(f"{args.config}: operators ready")
+    timed_opts = w.opts(w.timed, w.tol, w.gtol)
     for _ in range(args.warmup):
-        ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], mixed)
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        val, grad, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], mixed)
-        infos.append(info)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    value = args.steps / dt
+        w.run(timed_opts)
+    progress("warmup done")
+    dt, val, grad, infos = timed_runs(w, timed_opts, steps)
+    progress(f"{steps} timed steps: {dt / steps * 1e3:.1f} ms each")
+    value = steps / dt
+    one_eval = infos[-(len(infos) // steps):]
 
     kern_s = sum(i["loop_seconds"] for i in infos)
     kern_bytes = sum(i["bytes_model"] for i in infos)
     launches = sum(i["passes"] for i in infos)
     achieved = kern_bytes / kern_s / 1e9
-    last = infos[-1]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "pass2d_fast<float, R=2, no observations, 1 gradient> (fused 2-D pass)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": w.kernel,
                 "avg_launch_us": round(kern_s / launches * 1e6, 2),
                 "bytes_per_launch": round(kern_bytes / launches),
-                "bytes_model": "16 B per site per active probe (r and p read and written once, FP32)"}
-    if os.path.exists(TRAFFIC_FILE):
+                "bytes_model": "per site and active probe: r and p read and written once (4 x element size), "
+                               "plus each operator field once per launch"}
+    if args.config == "lattice512_sq" and os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if tr.get("kernel_hash") == kernel_hash():
@@ -173,52 +329,52 @@ def main():
             roofline["traffic_note"] = tr.get("note", "")
 
     out = {
-        "metric": "log det Q evals/s + SpMM HBM GB/s at rel. err 1e-4 vs FP64; fwd+grad",
+        "metric": METRIC,
         "value": round(value, 3),
         "unit": "evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "ms_per_step": round(dt / steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "lattice512_sq: 2-D 512x512 lattice, Q = (0.05 I + L)^2 (13-point), "
-                               "distance-4 modular colouring (41 probes), N=20 shifts, log det + d/dkappa2",
-                   "n": 512 * 512, "probes": last["ncolours"], "nshifts": 20, "tol": 1e-5, "grad_tol": 1e-6,
-                   "storage": "f32 vectors, f64 arithmetic", "iters_max": last["iters_max"],
-                   "parallelism": "one GPU"},
+        "config": {"workload": w.describe, "n": w.n, "probes": sum(i["ncolours"] for i in one_eval),
+                   "nshifts": 20, "tol": w.tol, "grad_tol": w.gtol,
+                   "storage": "f32 vectors, f64 arithmetic" if w.timed == ldq.LDQ_MIXED else "f64",
+                   "iters_max": max(i["iters_max"] for i in one_eval), "parallelism": "one GPU"},
         "roofline": roofline,
     }
 
     if not args.no_forms:
         # accuracy: the timed result against a tight FP64 run of the same library
-        tight = ldq.ldq_options_default(k=4, nshifts=20, tol=1e-10, grad_tol=1e-10, precision=ldq.LDQ_FP64)
-        ref_val, ref_grad, _ = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], tight)
-        # plain FP64 form at the same tolerances as the timed mixed form
-        fp64 = ldq.ldq_options_default(k=4, nshifts=20, tol=1e-5, grad_tol=1e-6, precision=ldq.LDQ_FP64)
-        ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], fp64)
-        torch.cuda.synchronize()
-        nf = max(2, args.steps // 3)
-        t1 = time.perf_counter()
-        for _ in range(nf):
-            fv, fg, finfo = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], fp64)
-        torch.cuda.synchronize()
-        fdt = (time.perf_counter() - t1) / nf
-        out["rel_err_vs_fp64"] = {"logdet": abs(val - ref_val) / abs(ref_val),
-                                  "grad": abs(grad[0] - ref_grad[0]) / abs(ref_grad[0])}
+        rv, rg, _ = w.run(w.opts(ldq.LDQ_FP64, 1e-10, 1e-10))
+        progress("tight FP64 reference done")
+        out["rel_err_vs_fp64"] = {"logdet": rel_err(val, rv), "grad": rel_err(grad, rg)}
+        if w.timed == ldq.LDQ_MIXED:
+            oname, oopts = "fp64", w.opts(ldq.LDQ_FP64, w.tol, w.gtol)
+        else:
+            oname, oopts = "mixed", w.opts(ldq.LDQ_MIXED, 1e-5, 1e-6)
+        w.run(oopts)
+        nf = max(1, steps // 3)
+        fdt, fv, fg, finf = timed_runs(w, oopts, nf)
+        tname = "mixed" if w.timed == ldq.LDQ_MIXED else "fp64"
         out["forms"] = {
-            "mixed": {"evals_per_s": round(value, 3), "ms": round(dt / args.steps * 1e3, 3),
-                      "gbs": round(achieved, 1), "iters_max": last["iters_max"]},
-            "fp64": {"evals_per_s": round(1.0 / fdt, 3), "ms": round(fdt * 1e3, 3),
-                     "gbs": round(finfo["bytes_model"] / finfo["loop_seconds"] / 1e9, 1),
-                     "iters_max": finfo["iters_max"],
-                     "rel_err_vs_tight_fp64": {"logdet": abs(fv - ref_val) / abs(ref_val),
-                                               "grad": abs(fg[0] - ref_grad[0]) / abs(ref_grad[0])}},
+            tname: {"evals_per_s": round(value, 3), "ms": round(dt / steps * 1e3, 3), "gbs": round(achieved, 1),
+                    "iters_max": out["config"]["iters_max"]},
+            oname: {"evals_per_s": round(nf / fdt, 3), "ms": round(fdt / nf * 1e3, 3),
+                    "gbs": round(sum(i["bytes_model"] for i in finf) / sum(i["loop_seconds"] for i in finf) / 1e9,
+                                 1),
+                    "iters_max": max(i["iters_max"] for i in finf),
+                    "rel_err_vs_tight_fp64": {"logdet": rel_err(fv, rv), "grad": rel_err(fg, rg)}},
         }
-        out["forms"].update(csr_forms(ctx, wl, nf, ref_val, ref_grad[0]))
+        progress(f"{oname} form done")
+        if args.config == "lattice512_sq":
+            out["forms"].update(csr_forms(ctx, w.wl, max(2, steps // 3), rv[0], rg[0][0]))
+            progress("CSR forms done")
+
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")    # 1 GiB
         b = torch.empty_like(a)
@@ -229,7 +385,8 @@ def main():
         out["copy_calibration_bytes"] = 2 * a.numel() * 4
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, last["iters_total"])
+        out["cpu_baseline"] = cpu_baseline(w, one_eval)
+        progress("CPU oracle sample done")
 
     ctx.close()
     print(json.dumps(out), flush=True)
