@@ -313,7 +313,9 @@ def main():
 
     kern_s = sum(i["loop_seconds"] for i in infos)
     kern_bytes = sum(i["bytes_model"] for i in infos)
-    launches = sum(i["passes"] for i in infos)
+    # a batched call shares its launches between fields: each field's info
+    # carries the batch's launch count
+    launches = (max(i["passes"] for i in one_eval) * steps) if w.batched else sum(i["passes"] for i in infos)
     achieved = kern_bytes / kern_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": w.kernel,

@@ -52,6 +52,9 @@ template <typename T> hipError_t launch_csr_pass_a(const PassCsr<T> &, int, bool
 template <typename T> hipError_t launch_csr_pass_b(const PassCsr<T> &, int, bool, hipStream_t);
 hipError_t launch_csr_tail(const TailArgs &, int, int, int, hipStream_t);
 hipError_t launch_lanczos_check(const double *, const ProbeState *, int, int, double, double, int *, hipStream_t);
+template <typename T> hipError_t launch_batch2d(const Batch2D<T> &, int, bool, int, hipStream_t);
+hipError_t launch_batch_compact(const FieldDesc *, const int32_t *, int, const ProbeState *, ProbeState *, WorkItem *,
+                                int *, hipStream_t);
 }  // namespace ldq
 
 using namespace ldq;
@@ -128,6 +131,7 @@ struct ldq_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   DevBuf vec, partials, pstate, sstate, shifts, classes, terms, stats, sums, misc, colbuf, jpkey, jpmask, hist;
+  DevBuf bfields, bitems, bwork;   // batched lattice passes
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<double> last_terms;
   int last_nparams = 0;
@@ -219,7 +223,8 @@ extern "C" void ldq_destroy(ldq_ctx *c) {
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
   for (DevBuf *b : {&c->vec, &c->partials, &c->pstate, &c->sstate, &c->shifts, &c->classes,
-                    &c->terms, &c->stats, &c->sums, &c->misc, &c->colbuf, &c->jpkey, &c->jpmask, &c->hist})
+                    &c->terms, &c->stats, &c->sums, &c->misc, &c->colbuf, &c->jpkey, &c->jpmask, &c->hist,
+                    &c->bfields, &c->bitems, &c->bwork})
     b->release();
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
@@ -1645,11 +1650,294 @@ extern "C" int ldq_probe_terms(ldq_ctx *c, double *out, int64_t capacity, int64_
   return LDQ_OK;
 }
 
+// ------------------------------------------------- many lattices at once
+// The batched STEP launches need every field to be a 2-D lattice of the same
+// kind with a constant shift, scale 1, no observation term and a modular
+// colouring of the same (C, a); derivative operators (at most one per field)
+// shifted Laplacians with a constant shift.
+static bool batchable(const std::vector<Call> &calls) {
+  if (calls.empty()) return false;
+  const Call &k0 = calls[0];
+  if (k0.nparams > 1) return false;
+  for (const Call &k : calls) {
+    const ldq_op *Q = k.Q;
+    if (Q->kind != OPK_LATTICE || Q->ndim != 2 || Q->field || Q->obs9 || Q->scale != 1.0) return false;
+    if (Q->lkind != k0.Q->lkind) return false;
+    if (k.col.colours || k.col.C != k0.col.C || k.col.a != k0.col.a) return false;
+    if (k.nparams != k0.nparams) return false;
+    if (k.nparams == 1) {
+      const ldq_op *d = k.dQ[0];
+      if (d->kind != OPK_LATTICE || d->lkind != LDQ_SHIFTED_LAPLACIAN || d->field || d->scale != k0.dQ[0]->scale)
+        return false;
+    }
+    if ((double)Q->n * 8.0 >= 4294967295.0) return false;
+  }
+  return true;
+}
+
+template <typename T>
+static int run_batched(ldq_ctx *c, std::vector<Call> &calls, double *logdet, double *grad, ldq_info *info) {
+  const int nf = (int)calls.size();
+  const Call &k0 = calls[0];
+  const int P = k0.nparams;
+  const int N = k0.o.nshifts;
+  const int nq = LDQ_NQ_BASE + P;
+  const bool sq = k0.Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN;
+  const int rows = pass2d_rows(sq, 32);
+  std::vector<FieldDesc> fd(nf);
+  std::vector<int32_t> item_field, classes;
+  int64_t vec_tot = 0, part_tot = 0, work_max = 0;
+  int items = 0;
+  for (int f = 0; f < nf; ++f) {
+    const Call &k = calls[f];
+    const int nb = (int)k.classes.size();
+    int tx = 0, nt = 0;
+    pass2d_tiles((int)k.Q->shape[0], (int)k.Q->shape[1], sq, rows, &tx, &nt);
+    fd[f] = FieldDesc{(int)k.Q->shape[0], (int)k.Q->shape[1], tx, nt, nb, items, vec_tot, part_tot, k.Q->kappa2,
+                      P ? k.dQ[0]->kappa2 : 0.0};
+    items += nb;
+    vec_tot += (int64_t)nb * k.Q->n;
+    part_tot += (int64_t)nb * nq * nt;
+    work_max += (int64_t)nb * nt;
+    for (int j = 0; j < nb; ++j) {
+      item_field.push_back(f);
+      classes.push_back(k.classes[j]);
+    }
+  }
+  if (work_max >= INT32_MAX || items == 0) return fail(LDQ_E_UNSUPPORTED, "batch too large for one work list");
+  const int hcap = hist_cap(items, k0.o.max_iter);
+  CHK(c->vec.reserve(4 * (size_t)vec_tot * sizeof(T)));
+  CHK(c->partials.reserve(2 * (size_t)part_tot * sizeof(double)));
+  CHK(c->pstate.reserve(2 * (size_t)items * sizeof(ProbeState)));
+  CHK(c->sstate.reserve((size_t)items * N * sizeof(ShiftState)));
+  CHK(c->hist.reserve((size_t)items * hcap * 2 * sizeof(double)));
+  CHK(c->shifts.reserve((size_t)nf * 2 * LDQ_MAXN * sizeof(cplx)));
+  CHK(c->classes.reserve((size_t)items * sizeof(int32_t)));
+  CHK(c->terms.reserve((size_t)items * (1 + P) * sizeof(double)));
+  CHK(c->stats.reserve((size_t)nf * 8 * sizeof(int)));
+  CHK(c->sums.reserve((size_t)nf * (1 + P) * sizeof(double)));
+  CHK(c->misc.reserve(8 * sizeof(int)));
+  CHK(c->bfields.reserve((size_t)nf * sizeof(FieldDesc)));
+  CHK(c->bitems.reserve((size_t)items * sizeof(int32_t)));
+  CHK(c->bwork.reserve((size_t)work_max * sizeof(WorkItem)));
+  T *vec = c->vec.as<T>();
+  T *bufA_r = vec, *bufA_p = vec + vec_tot, *bufB_r = vec + 2 * vec_tot, *bufB_p = vec + 3 * vec_tot;
+  cplx *sig = c->shifts.as<cplx>(), *coef = sig + (size_t)nf * LDQ_MAXN;
+  double *part[2] = {c->partials.as<double>(), c->partials.as<double>() + part_tot};
+  ProbeState *st[2] = {c->pstate.as<ProbeState>(), c->pstate.as<ProbeState>() + items};
+  int *counter = c->misc.as<int>();          // work-list length
+  int *dummy_active = counter + 1;           // the per-probe countdown is not used here
+  HIPCHK(hipMemcpyAsync(c->bfields.ptr, fd.data(), nf * sizeof(FieldDesc), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->bitems.ptr, item_field.data(), items * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->classes.ptr, classes.data(), items * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemsetAsync(c->stats.ptr, 0, (size_t)nf * 8 * sizeof(int), c->stream));
+  for (int f = 0; f < nf; ++f)
+    HIPCHK(launch_shifts(calls[f].lmin, calls[f].lmax, N, sig + (size_t)f * LDQ_MAXN, coef + (size_t)f * LDQ_MAXN,
+                         c->stream));
+  HIPCHK(launch_init_probes(st[0], items, c->classes.as<int32_t>(), dummy_active, c->stream));
+
+  TailArgs ta{};
+  ta.sh = c->sstate.as<ShiftState>();
+  ta.nshifts = N;
+  ta.ngrad = P;
+  ta.tol2 = k0.o.tol * k0.o.tol;
+  const double gt = k0.o.grad_tol > 0.0 ? k0.o.grad_tol : k0.o.tol;
+  ta.grad_tol2 = gt * gt;
+  ta.max_iter = k0.o.max_iter;
+  ta.active_count = dummy_active;
+  ta.need_base = P > 0;
+  ta.hist = c->hist.as<double>();
+  ta.hist_cap = hcap;
+
+  HIPCHK(hipEventRecord(c->ev0, c->stream));
+  // INIT and FIRST, one field at a time (the single-lattice generic pass on the
+  // field's slice of every buffer)
+  for (int f = 0; f < nf; ++f) {
+    const FieldDesc &d = fd[f];
+    Pass2D<T> a{};
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.tiles_x = d.tiles_x;
+    a.ntiles = d.ntiles;
+    a.rows = rows;
+    a.nprobes = d.nprobes;
+    a.colC = k0.col.C;
+    a.cola = k0.col.a;
+    a.kappa2 = d.kappa2;
+    a.scale = 1.0;
+    if (P) {
+      a.grad[0].kind = GK_SHIFTED;
+      a.grad[0].scale = k0.dQ[0]->scale;
+      a.grad[0].kappa2 = d.kd;
+    }
+    TailArgs t = ta;
+    t.sh = ta.sh + (size_t)d.item_base * N;
+    t.sigma = sig + (size_t)f * LDQ_MAXN;
+    t.hist = ta.hist + (size_t)d.item_base * hcap * 2;
+    for (int mode : {(int)MODE_INIT, (int)MODE_FIRST}) {
+      t.st_in = st[0] + d.item_base;
+      t.st_out = st[1] + d.item_base;
+      t.part_in = part[0] + d.part_off;
+      t.part_out = (mode == MODE_INIT ? part[0] : part[1]) + d.part_off;
+      a.tail = t;
+      a.mode = mode;
+      a.r_in = a.p_in = nullptr;
+      a.r_out = mode == MODE_INIT ? nullptr : bufA_r + d.vec_off;
+      a.p_out = mode == MODE_INIT ? nullptr : bufA_p + d.vec_off;
+      HIPCHK(launch_pass2d<T>(a, sq, false, false, c->stream));
+    }
+  }
+  Batch2D<T> b{};
+  b.work = c->bwork.as<WorkItem>();
+  b.fields = c->bfields.as<FieldDesc>();
+  b.sigma = sig;
+  b.rows = rows;
+  b.colC = k0.col.C;
+  b.cola = k0.col.a;
+  b.gscale = P ? k0.dQ[0]->scale : 0.0;
+  b.tail = ta;
+  // work list from the states in st[1]; stopped items' states go to st[0] too
+  auto compact = [&](int *h_count) -> int {
+    HIPCHK(hipMemsetAsync(counter, 0, sizeof(int), c->stream));
+    HIPCHK(launch_batch_compact(c->bfields.as<FieldDesc>(), c->bitems.as<int32_t>(), items, st[1], st[0],
+                                c->bwork.as<WorkItem>(), counter, c->stream));
+    HIPCHK(hipMemcpyAsync(h_count, counter, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LDQ_OK;
+  };
+  HIPCHK(hipEventRecord(c->ev1, c->stream));
+  int nwork = 0;
+  CHK(compact(&nwork));
+  double kernel_ms = 0.0;
+  {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    kernel_ms += ms;
+  }
+  const int check = k0.o.check_every > 0 ? 2 * ((k0.o.check_every + 1) / 2) : 16;
+  int64_t launches = 2 * (int64_t)nf, steps = 0;
+  int64_t tiles_run = 0;
+  bool stalled = false;
+  while (nwork > 0) {
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
+    for (int i = 0; i < check; ++i) {
+      const int in = (i % 2 == 0) ? 1 : 0;
+      b.tail.st_in = st[in];
+      b.tail.st_out = st[1 - in];
+      b.tail.part_in = part[in];
+      b.tail.part_out = part[1 - in];
+      b.r_in = in ? bufA_r : bufB_r;
+      b.p_in = in ? bufA_p : bufB_p;
+      b.r_out = in ? bufB_r : bufA_r;
+      b.p_out = in ? bufB_p : bufA_p;
+      HIPCHK(launch_batch2d<T>(b, nwork, sq, P, c->stream));
+    }
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    launches += check;
+    steps += check;
+    tiles_run += (int64_t)check * nwork;
+    CHK(compact(&nwork));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    kernel_ms += ms;
+    if (steps > (int64_t)k0.o.max_iter + 2 * check) {
+      stalled = true;
+      break;
+    }
+  }
+  // per field: terms, enclosure check, sums (fixed order)
+  for (int f = 0; f < nf; ++f) {
+    const FieldDesc &d = fd[f];
+    double clo, chi;
+    check_interval(calls[f].lmin, calls[f].lmax, (int)sizeof(T), &clo, &chi);
+    int *sf = c->stats.as<int>() + (size_t)f * 8;
+    HIPCHK(launch_lanczos_check(ta.hist + (size_t)d.item_base * hcap * 2, st[1] + d.item_base, d.nprobes, hcap, clo,
+                                chi, sf, c->stream));
+    double *tf = c->terms.as<double>() + (size_t)d.item_base * (1 + P);
+    HIPCHK(launch_probe_terms(st[1] + d.item_base, ta.sh + (size_t)d.item_base * N, coef + (size_t)f * LDQ_MAXN,
+                              d.nprobes, N, P, tf, 0, sf, c->stream));
+    HIPCHK(launch_sum_terms(tf, d.nprobes, 1 + P, c->sums.as<double>() + (size_t)f * (1 + P), c->stream));
+  }
+  std::vector<double> sums((size_t)nf * (1 + P));
+  std::vector<int> stats((size_t)nf * 8);
+  HIPCHK(hipMemcpyAsync(sums.data(), c->sums.ptr, sums.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(stats.data(), c->stats.ptr, stats.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  c->last_terms.resize((size_t)items * (1 + P));
+  HIPCHK(hipMemcpyAsync(c->last_terms.data(), c->terms.ptr, c->last_terms.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->last_nparams = P;
+  c->last_count = items;
+  // algorithmic bytes per field: r and p read and written once per probe-site
+  // and iteration (the first pass writes only)
+  std::vector<double> bytes(nf);
+  double bytes_tot = 0.0;
+  int worst = 0;
+  for (int f = 0; f < nf; ++f) {
+    const int *sf = stats.data() + (size_t)f * 8;
+    int64_t it_tot;
+    std::memcpy(&it_tot, sf + 2, sizeof it_tot);
+    const double n = (double)fd[f].nx * fd[f].ny;
+    bytes[f] = (double)sizeof(T) * n * (4.0 * (double)it_tot - 2.0 * fd[f].nprobes);
+    bytes_tot += bytes[f];
+    worst = std::max(worst, sf[0]);
+    logdet[f] = sums[(size_t)f * (1 + P)];
+    for (int i = 0; i < P; ++i) grad[(size_t)f * P + i] = sums[(size_t)f * (1 + P) + 1 + i];
+  }
+  if (info) {
+    for (int f = 0; f < nf; ++f) {
+      const int *sf = stats.data() + (size_t)f * 8;
+      ldq_info &o = info[f];
+      o = ldq_info{};
+      o.ncolours = fd[f].nprobes;
+      o.iters_max = sf[1];
+      std::memcpy(&o.iters_total, sf + 2, sizeof o.iters_total);
+      o.lambda_min = calls[f].lmin;
+      o.lambda_max = calls[f].lmax;
+      uint64_t rb;
+      std::memcpy(&rb, sf + 6, sizeof rb);
+      o.max_rel_residual = __builtin_bit_cast(double, rb);
+      o.enclosure_violations = sf[4];
+      // the launches are shared: each field gets the share of the device time
+      // of its algorithmic bytes, and the batch's launch count
+      o.loop_seconds = bytes_tot > 0.0 ? kernel_ms * 1e-3 * bytes[f] / bytes_tot : 0.0;
+      o.passes = launches;
+      o.probe_passes = o.iters_total;
+      o.bytes_model = bytes[f];
+    }
+  }
+  (void)tiles_run;
+  if (stalled) return fail(LDQ_E_NO_CONVERGENCE, "probes did not stop within max_iter");
+  if (worst == 2) return fail(LDQ_E_NOT_SPD, "the Krylov recurrence met p^T Q p <= 0 or a non-finite value");
+  if (worst == 3) return fail(LDQ_E_NO_CONVERGENCE, "max_iter = %d reached before every shift converged",
+                              k0.o.max_iter);
+  return LDQ_OK;
+}
+
 extern "C" int ldq_logdet_batched(ldq_ctx *c, int nfields, const ldq_op *const *Q, int nparams,
                                   const ldq_op *const *dQ, const ldq_options *opts, double *logdet, double *grad,
                                   ldq_info *info) {
   if (!c || nfields < 0 || (nfields > 0 && (!Q || !logdet)) || (nparams > 0 && (!dQ || !grad)))
     return fail(LDQ_E_INVALID, "invalid batched arguments");
+  if (nfields == 0) return LDQ_OK;
+  {
+    // one set of batched launches when every field qualifies
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<Call> calls(nfields);
+    bool ok = true;
+    for (int f = 0; f < nfields && ok; ++f) {
+      CHK(prepare_call(calls[f], c, Q[f], nparams, nparams ? dQ + (size_t)f * nparams : nullptr, opts));
+      ok = calls[f].o.precision == calls[0].o.precision;
+    }
+    if (ok && batchable(calls)) {
+      const int st = calls[0].o.precision == LDQ_MIXED ? run_batched<float>(c, calls, logdet, grad, info)
+                                                       : run_batched<double>(c, calls, logdet, grad, info);
+      const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (info)
+        for (int f = 0; f < nfields; ++f) info[f].seconds = secs;
+      return st;
+    }
+  }
   int worst = LDQ_OK;
   for (int f = 0; f < nfields; ++f) {
     int st = logdet_impl(c, Q[f], nparams, nparams ? dQ + (size_t)f * nparams : nullptr, opts, logdet + f,

@@ -137,6 +137,37 @@ struct Pass3D {
   TailArgs tail;
 };
 
+// Many independent 2-D lattices advanced together: every STEP launch covers
+// the (field, probe, tile) entries of a work list that holds the tiles of the
+// probes still iterating.  Field f's probes are items item_base .. item_base
+// + nprobes - 1 (probe states, shift states, history), its vectors start at
+// element vec_off of each vector buffer (probe j at vec_off + j n) and its
+// partials at part_off of each partial buffer (probe j at part_off + j nq
+// ntiles).
+struct FieldDesc {
+  int nx, ny, tiles_x, ntiles;
+  int nprobes, item_base;
+  int64_t vec_off, part_off;
+  double kappa2;        // Q = (kappa2 I + L)^p
+  double kd;            // derivative: gscale (kd I + L)
+};
+
+struct WorkItem {
+  int field, probe, tile, pad;
+};
+
+template <typename T>
+struct Batch2D {
+  const WorkItem *work;
+  const FieldDesc *fields;
+  const cplx *sigma;    // [field][LDQ_MAXN]
+  int rows, colC, cola;
+  double gscale;
+  const T *r_in, *p_in;
+  T *r_out, *p_out;
+  TailArgs tail;        // part_in/part_out/st_in/st_out/sh/hist are the buffer bases
+};
+
 // General sparse operator.  The rows are cut into slices of 64 (one wave
 // each); slice s stores its entries column-major, entry k of row 64 s + l at
 // sptr[s] + 64 k + l, for k below the slice width (sptr[s+1] - sptr[s]) / 64.

@@ -75,7 +75,8 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
   const int lane = threadIdx.x;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int probe = L / a.ntiles, tile = L - probe * a.ntiles;
-  const Step step = pass_prologue<1>(a.tail, probe, tile, a.ntiles, a.mode);
+  const ProbeRef pref = probe_ref(a.tail, probe, a.ntiles);
+  const Step step = pass_prologue<1>(a.tail, pref, tile, a.ntiles, a.mode);
   if (!step.run) return;
   const int colour = step.colour;
   // GEN: r_k = p_k = v_j generated from the colouring (INIT: alpha = 0, nothing stored)
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
       ay_d = advance(ay_d);
     }
   }
-  pass_epilogue_n<NQ>(a.tail, probe, tile, a.ntiles, q);
+  pass_epilogue_n<NQ>(pref, tile, a.ntiles, q);
 }
 
 // Specialised STEP pass for the common case: modular colouring, constant
@@ -320,23 +321,65 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
 // unconditional (clamped addresses, values selected afterwards), so the
 // compiler can keep the five-row prefetch in flight instead of waiting for all
 // outstanding loads at every conditional.
+// Geometry and coefficients of one probe's tile for fast_tile.
+template <typename T>
+struct FastTile {
+  int nx, ny, tiles_x, rows;
+  int colC, cola;
+  double kappa2;       // Q's constant shift
+  double kd;           // gradient 0: shift of the derivative Laplacian
+  double gs0, gs1;     // gradient scales
+  double tau;          // observation weight
+  const T *obs;        // observation planes (9 x n)
+  const T *r_in, *p_in;
+  T *r_out, *p_out;    // the probe's vectors
+};
+
+template <typename T, int R, bool OBS, int NG>
+__device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, double alpha, double beta, double *q);
+
 template <typename T, int R, bool OBS, int NG>
 __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
-  constexpr int W = 64 - 4 * R;
   constexpr int NQ = LDQ_NQ_BASE + NG;
-  const int lane = threadIdx.x;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int probe = L / a.ntiles, tile = L - probe * a.ntiles;
-
-  const Step step = pass_prologue<1>(a.tail, probe, tile, a.ntiles, MODE_STEP);
+  const ProbeRef pref = probe_ref(a.tail, probe, a.ntiles);
+  const Step step = pass_prologue<1>(a.tail, pref, tile, a.ntiles, MODE_STEP);
   if (!step.run) return;
-  const int colour = __builtin_amdgcn_readfirstlane(step.colour);
-  const double alpha = step.alpha, beta = step.beta;
+  const size_t off = (size_t)probe * a.nx * a.ny;
+  FastTile<T> ft;
+  ft.nx = a.nx;
+  ft.ny = a.ny;
+  ft.tiles_x = a.tiles_x;
+  ft.rows = a.rows;
+  ft.colC = a.colC;
+  ft.cola = a.cola;
+  ft.kappa2 = a.kappa2;
+  ft.kd = NG > 0 ? a.grad[0].kappa2 : 0.0;
+  ft.gs0 = NG > 0 ? a.grad[0].scale : 0.0;
+  ft.gs1 = NG > 1 ? a.grad[1].scale : 0.0;
+  ft.tau = a.tau;
+  ft.obs = a.obs;
+  ft.r_in = a.r_in + off;
+  ft.p_in = a.p_in + off;
+  ft.r_out = a.r_out + off;
+  ft.p_out = a.p_out + off;
+  double q[NQ];
+  fast_tile<T, R, OBS, NG>(ft, tile, __builtin_amdgcn_readfirstlane(step.colour), step.alpha, step.beta, q);
+  pass_epilogue_n<NQ>(pref, tile, a.ntiles, q);
+}
+
+// One tile of one probe: the march of the fused pass; q[] receives this
+// wave's sums of the pass's dot products.
+template <typename T, int R, bool OBS, int NG>
+__device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, double alpha, double beta, double *q) {
+  constexpr int W = 64 - 4 * R;
+  constexpr int NQ = LDQ_NQ_BASE + NG;
+  const int lane = threadIdx.x & 63;
   const T beta_t = (T)beta;
 
   const int nx = a.nx, ny = a.ny;
   const size_t n = (size_t)nx * ny;
-  const size_t off = (size_t)probe * n;
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int x0 = tx * W, y0 = ty * a.rows;
   const int yb = min(y0 + a.rows, ny);
@@ -349,9 +392,9 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
   const int degx = (x > 0) + (x < nx - 1);
   const double c = a.kappa2 + 4.0;
   const double m2c = -2.0 * c;
-  const double kd = NG > 0 ? a.grad[0].kappa2 + 4.0 : 0.0;
-  const double gs0 = NG > 0 ? a.grad[0].scale : 0.0;
-  const double gs1 = NG > 1 ? a.grad[1].scale : 0.0;
+  const double kd = NG > 0 ? a.kd + 4.0 : 0.0;
+  const double gs0 = a.gs0;
+  const double gs1 = a.gs1;
   // A tile is interior when every column and every row it touches (prefetch
   // included) has all four axis neighbours inside the lattice: no masking and
   // a constant 13-point diagonal there.
@@ -379,15 +422,14 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
 
   // buffer resources over this probe's vectors and the observation planes
   const unsigned vbytes = (unsigned)(n * sizeof(T));
-  const __amdgpu_buffer_rsrc_t rs_rin = make_rsrc(a.r_in + off, vbytes);
-  const __amdgpu_buffer_rsrc_t rs_pin = make_rsrc(a.p_in + off, vbytes);
-  const __amdgpu_buffer_rsrc_t rs_rout = make_rsrc(a.r_out + off, vbytes);
-  const __amdgpu_buffer_rsrc_t rs_pout = make_rsrc(a.p_out + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_rin = make_rsrc(a.r_in, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_pin = make_rsrc(a.p_in, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_rout = make_rsrc(a.r_out, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_pout = make_rsrc(a.p_out, vbytes);
   const __amdgpu_buffer_rsrc_t rs_obs = make_rsrc(OBS ? a.obs : a.r_in, OBS ? 9u * vbytes : vbytes);
   const unsigned lx = (unsigned)xc * (unsigned)sizeof(T);           // lane byte offset
   const unsigned rowb = (unsigned)nx * (unsigned)sizeof(T);         // row stride in bytes
 
-  double q[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) q[i] = 0.0;
 
@@ -547,7 +589,84 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
     march(std::true_type{});
   else
     march(std::false_type{});
-  pass_epilogue_n<NQ>(a.tail, probe, tile, a.ntiles, q);
+}
+
+// Batched STEP pass: one wave per work-list entry (field, probe, tile).
+template <typename T, int R, int NG>
+__global__ __launch_bounds__(64) void batch2d_fast(Batch2D<T> b) {
+  constexpr int NQ = LDQ_NQ_BASE + NG;
+  const WorkItem wk = b.work[xcd_remap(blockIdx.x, gridDim.x)];
+  const FieldDesc fd = b.fields[wk.field];
+  const size_t po = (size_t)fd.part_off + (size_t)wk.probe * NQ * fd.ntiles;
+  const ProbeRef pref{fd.item_base + wk.probe, b.tail.part_in + po, b.tail.part_out + po,
+                      b.sigma + (size_t)wk.field * LDQ_MAXN};
+  const Step step = pass_prologue<1>(b.tail, pref, wk.tile, fd.ntiles, MODE_STEP);
+  if (!step.run) return;
+  const size_t off = (size_t)fd.vec_off + (size_t)wk.probe * fd.nx * fd.ny;
+  FastTile<T> ft;
+  ft.nx = fd.nx;
+  ft.ny = fd.ny;
+  ft.tiles_x = fd.tiles_x;
+  ft.rows = b.rows;
+  ft.colC = b.colC;
+  ft.cola = b.cola;
+  ft.kappa2 = fd.kappa2;
+  ft.kd = fd.kd;
+  ft.gs0 = b.gscale;
+  ft.gs1 = 0.0;
+  ft.tau = 0.0;
+  ft.obs = nullptr;
+  ft.r_in = b.r_in + off;
+  ft.p_in = b.p_in + off;
+  ft.r_out = b.r_out + off;
+  ft.p_out = b.p_out + off;
+  double q[NQ];
+  fast_tile<T, R, false, NG>(ft, wk.tile, __builtin_amdgcn_readfirstlane(step.colour), step.alpha, step.beta, q);
+  pass_epilogue_n<NQ>(pref, wk.tile, fd.ntiles, q);
+}
+
+template <typename T>
+hipError_t launch_batch2d(const Batch2D<T> &b, int nwork, bool squared, int ngrad, hipStream_t stream) {
+  if (nwork <= 0) return hipSuccess;
+  if (squared) {
+    if (ngrad == 0) hipLaunchKernelGGL((batch2d_fast<T, 2, 0>), dim3(nwork), dim3(64), 0, stream, b);
+    else hipLaunchKernelGGL((batch2d_fast<T, 2, 1>), dim3(nwork), dim3(64), 0, stream, b);
+  } else {
+    if (ngrad == 0) hipLaunchKernelGGL((batch2d_fast<T, 1, 0>), dim3(nwork), dim3(64), 0, stream, b);
+    else hipLaunchKernelGGL((batch2d_fast<T, 1, 1>), dim3(nwork), dim3(64), 0, stream, b);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_batch2d<float>(const Batch2D<float> &, int, bool, int, hipStream_t);
+template hipError_t launch_batch2d<double>(const Batch2D<double> &, int, bool, int, hipStream_t);
+
+// Work list of the probes still iterating: each active item appends its
+// tiles (the order of items in the list varies from run to run; every tile
+// writes fixed slots, so results do not).  An item that has stopped gets its
+// final state copied into the other state buffer, since no later launch
+// carries it forward.
+__global__ void batch_compact_kernel(const FieldDesc *fields, const int32_t *item_field, int nitems,
+                                     const ProbeState *st_cur, ProbeState *st_other, WorkItem *work, int *count) {
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= nitems) return;
+  const ProbeState ps = st_cur[item];
+  if (!ps.active) {
+    st_other[item] = ps;
+    return;
+  }
+  const int f = item_field[item];
+  const FieldDesc fd = fields[f];
+  const int base = atomicAdd(count, fd.ntiles);
+  for (int t = 0; t < fd.ntiles; ++t) work[base + t] = WorkItem{f, item - fd.item_base, t, 0};
+}
+
+hipError_t launch_batch_compact(const FieldDesc *fields, const int32_t *item_field, int nitems,
+                                const ProbeState *st_cur, ProbeState *st_other, WorkItem *work, int *count,
+                                hipStream_t stream) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_compact_kernel, dim3((nitems + 255) / 256), dim3(256), 0, stream, fields, item_field,
+                     nitems, st_cur, st_other, work, count);
+  return hipGetLastError();
 }
 
 template <typename T, int R, bool OBS, bool GEN>

@@ -29,7 +29,8 @@ __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
 
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int probe = L / a.ntiles, tile = L - probe * a.ntiles;
-  const Step step = pass_prologue<LDQ_BLOCK / 64>(a.tail, probe, tile, a.ntiles, a.mode);
+  const ProbeRef pref = probe_ref(a.tail, probe, a.ntiles);
+  const Step step = pass_prologue<LDQ_BLOCK / 64>(a.tail, pref, tile, a.ntiles, a.mode);
   if (!step.run) return;
   const int colour = step.colour;
   const double alpha = step.alpha, beta = step.beta;
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
       if (t - 1 >= z0) dots_plane(t - 1);
     }
   }
-  pass_epilogue<LDQ_BLOCK / 64>(a.tail, probe, tile, a.ntiles, q);
+  pass_epilogue<LDQ_BLOCK / 64>(a.tail, pref, tile, a.ntiles, q);
 }
 
 template <typename T>

@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void csr_pass_b_kernel(PassCsr<T> a) {
 // One wave per probe: reduce the partials of passes A and B, advance the base
 // CG scalars, every shift and the gradient sums (state updated in place).
 __global__ __launch_bounds__(64) void csr_tail_kernel(TailArgs ta, int ntiles, int mode) {
-  (void)pass_prologue<1>(ta, blockIdx.x, 0, ntiles, mode);
+  (void)pass_prologue<1>(ta, probe_ref(ta, blockIdx.x, ntiles), 0, ntiles, mode);
 }
 
 static unsigned csr_grid(int nslices) { return (unsigned)((nslices + 3) / 4); }

@@ -54,6 +54,22 @@ __device__ inline void block_sum(const double *q, int nq, double *out) {
   }
 }
 
+// Where one probe's data lives: its index into the probe states, shift states
+// and Lanczos history, its partial sums ([quantity][tile]) in the input and
+// output partial buffers, and the shifts of its operator.
+struct ProbeRef {
+  int st;
+  const double *pin;
+  double *pout;
+  const cplx *sigma;
+};
+
+// The layout of a single-operator launch: probe j's partials at j * nq * ntiles.
+__device__ inline ProbeRef probe_ref(const TailArgs &ta, int probe, int ntiles) {
+  const size_t o = (size_t)probe * (LDQ_NQ_BASE + ta.ngrad) * ntiles;
+  return ProbeRef{probe, ta.part_in + o, ta.part_out + o, ta.sigma};
+}
+
 struct Step {
   bool run;       // this workgroup performs the pass
   int colour;     // colour class of the probe
@@ -67,15 +83,15 @@ struct Step {
 //   psi += alpha_k (zeta_{k+1} / zeta_k) phi
 //   phi  = zeta_{k+1} rho' + (zeta_{k+1} / zeta_k)^2 beta_k phi
 // psi accumulates v^T x^sigma and phi tracks v^T p^sigma (scalar-only CG-M).
-__device__ inline bool shifts_update(const TailArgs &ta, int probe, double ak, double akm1, double bkm1, double bk,
-                                     double gn, double rhon, double vnorm2, bool *bad_out) {
+__device__ inline bool shifts_update(const TailArgs &ta, const ProbeRef &pr, double ak, double akm1, double bkm1,
+                                     double bk, double gn, double rhon, double vnorm2, bool *bad_out) {
   const int lane = threadIdx.x & 63;
   bool frozen = true, bad = false;
   if (lane < ta.nshifts) {
-    ShiftState *sp = ta.sh + (size_t)probe * ta.nshifts + lane;
+    ShiftState *sp = ta.sh + (size_t)pr.st * ta.nshifts + lane;
     ShiftState s = *sp;
     if (!s.frozen) {
-      const cplx sig = ta.sigma[lane];
+      const cplx sig = pr.sigma[lane];
       const cplx one_m = cmk(1.0 - sig.re * ak, -sig.im * ak);
       const cplx den = cadd(cscale(csub(s.zeta_prev, s.zeta), ak * bkm1), cmul(cscale(s.zeta_prev, akm1), one_m));
       const cplx znext = cdiv(cscale(cmul(s.zeta, s.zeta_prev), akm1), den);
@@ -98,12 +114,12 @@ __device__ inline bool shifts_update(const TailArgs &ta, int probe, double ak, d
 // scalars, decide whether it is finished.  Called by every thread of the
 // workgroup (NW waves; one tile per workgroup).
 template <int NW>
-__device__ inline Step pass_prologue(const TailArgs &ta, int probe, int tile, int ntiles, int mode) {
+__device__ inline Step pass_prologue(const TailArgs &ta, const ProbeRef &pr, int tile, int ntiles, int mode) {
   double tot[LDQ_NQ_MAX];
-  const ProbeState in = ta.st_in[probe];
+  const ProbeState in = ta.st_in[pr.st];
   Step step{false, in.colour, 0.0, 0.0};
   if (!in.active) {
-    if (tile == 0 && threadIdx.x == 0) ta.st_out[probe] = in;    // carry the final state forward
+    if (tile == 0 && threadIdx.x == 0) ta.st_out[pr.st] = in;    // carry the final state forward
     return step;
   }
   if (mode == MODE_INIT) {
@@ -116,7 +132,7 @@ __device__ inline Step pass_prologue(const TailArgs &ta, int probe, int tile, in
   double acc[LDQ_NQ_MAX];
 #pragma unroll
   for (int i = 0; i < LDQ_NQ_MAX; ++i) acc[i] = 0.0;
-  const double *src = ta.part_in + (size_t)probe * nq * ntiles;
+  const double *src = pr.pin;
   for (int t = threadIdx.x; t < ntiles; t += NW * 64) {
 #pragma unroll
     for (int i = 0; i < LDQ_NQ_MAX; ++i)
@@ -153,7 +169,7 @@ __device__ inline Step pass_prologue(const TailArgs &ta, int probe, int tile, in
       s.psi = cmk(0.0, 0.0);
       s.frozen = done ? 1 : 0;
       s.pad = 0;
-      ta.sh[(size_t)probe * ta.nshifts + threadIdx.x] = s;
+      ta.sh[(size_t)pr.st * ta.nshifts + threadIdx.x] = s;
     }
     step.alpha = ps.alpha;
     step.beta = 0.0;                               // beta_{-1} = 0: p_0 = r_0
@@ -166,11 +182,11 @@ __device__ inline Step pass_prologue(const TailArgs &ta, int probe, int tile, in
     if (owner) {
       bool bad = false;
       if constexpr (NW == 1) {
-        all_frozen = shifts_update(ta, probe, ak, akm1, bkm1, bk, gn, tot[2], ps.vnorm2, &bad);
+        all_frozen = shifts_update(ta, pr, ak, akm1, bkm1, bk, gn, tot[2], ps.vnorm2, &bad);
       } else {
         __shared__ int sh_flags[2];
         if (threadIdx.x < 64) {
-          const bool f = shifts_update(ta, probe, ak, akm1, bkm1, bk, gn, tot[2], ps.vnorm2, &bad);
+          const bool f = shifts_update(ta, pr, ak, akm1, bkm1, bk, gn, tot[2], ps.vnorm2, &bad);
           if (threadIdx.x == 0) {
             sh_flags[0] = f;
             sh_flags[1] = bad;
@@ -222,11 +238,11 @@ __device__ inline Step pass_prologue(const TailArgs &ta, int probe, int tile, in
       // the CG coefficients define the Lanczos tridiagonal matrix of the probe
       // (diagonal 1/alpha_i + beta_{i-1}/alpha_{i-1}, off-diagonal
       // sqrt(beta_{i-1})/alpha_{i-1}); its eigenvalues lie in the spectrum of Q
-      double *h = ta.hist + ((size_t)probe * ta.hist_cap + ps.iter) * 2;
+      double *h = ta.hist + ((size_t)pr.st * ta.hist_cap + ps.iter) * 2;
       h[0] = ps.alpha;
       h[1] = mode == MODE_FIRST ? 0.0 : ps.beta_prev;
     }
-    ta.st_out[probe] = ps;
+    ta.st_out[pr.st] = ps;
   }
   step.run = !done;
   return step;
@@ -234,24 +250,24 @@ __device__ inline Step pass_prologue(const TailArgs &ta, int probe, int tile, in
 
 // End of a pass: the workgroup's sums of the nq quantities go to part_out.
 template <int NW>
-__device__ inline void pass_epilogue(const TailArgs &ta, int probe, int tile, int ntiles, const double *q) {
+__device__ inline void pass_epilogue(const TailArgs &ta, const ProbeRef &pr, int tile, int ntiles, const double *q) {
   double tot[LDQ_NQ_MAX];
   const int nq = LDQ_NQ_BASE + ta.ngrad;
   block_sum<NW>(q, nq, tot);
   if (threadIdx.x == 0) {
-    for (int i = 0; i < nq; ++i) ta.part_out[((size_t)probe * nq + i) * ntiles + tile] = tot[i];
+    for (int i = 0; i < nq; ++i) pr.pout[(size_t)i * ntiles + tile] = tot[i];
   }
 }
 
 // Single-wave epilogue with a compile-time number of quantities.
 template <int NQ>
-__device__ inline void pass_epilogue_n(const TailArgs &ta, int probe, int tile, int ntiles, const double *q) {
+__device__ inline void pass_epilogue_n(const ProbeRef &pr, int tile, int ntiles, const double *q) {
   double tot[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) tot[i] = wave_sum(q[i]);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) ta.part_out[((size_t)probe * NQ + i) * ntiles + tile] = tot[i];
+    for (int i = 0; i < NQ; ++i) pr.pout[(size_t)i * ntiles + tile] = tot[i];
   }
 }
 
