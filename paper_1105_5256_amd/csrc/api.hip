@@ -968,7 +968,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   // tiles
   int tiles_x = 0, tiles_y = 0, nzseg = 0, ntiles = 0;
   const int zseg = 32;
-  const int rows2d = pass2d_rows(Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN, 32);
+  const int rows2d = pass2d_rows(Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN, LDQ_ROWS2D);
   if (is3d)
     pass3d_tiles((int)Q->shape[0], (int)Q->shape[1], (int)Q->shape[2], zseg, &tiles_x, &tiles_y, &nzseg, &ntiles);
   else
@@ -1683,7 +1683,7 @@ static int run_batched(ldq_ctx *c, std::vector<Call> &calls, double *logdet, dou
   const int N = k0.o.nshifts;
   const int nq = LDQ_NQ_BASE + P;
   const bool sq = k0.Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN;
-  const int rows = pass2d_rows(sq, 32);
+  const int rows = pass2d_rows(sq, LDQ_ROWS2D);
   std::vector<FieldDesc> fd(nf);
   std::vector<int32_t> item_field, classes;
   int64_t vec_tot = 0, part_tot = 0, work_max = 0;

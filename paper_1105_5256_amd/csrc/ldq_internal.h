@@ -7,7 +7,9 @@
 #define LDQ_MAXP 4          // derivative operators per call
 #define LDQ_MAXN 64         // shifts per call (one wave64 lane per shift)
 #define LDQ_BLOCK 256       // threads per workgroup of the pass kernels
-#define LDQ_ROWS2D 32      // rows per wave tile of the 2-D pass (rows + 4R is a multiple of 5)
+#ifndef LDQ_ROWS2D
+#define LDQ_ROWS2D 32      // rows per wave tile of the 2-D pass (rounded up so that rows + 4R is a multiple of 5)
+#endif
 #define LDQ_NQ_BASE 3       // reduced quantities of a pass: gamma, delta, rho (+ one omega per parameter)
 
 namespace ldq {

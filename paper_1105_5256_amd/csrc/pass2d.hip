@@ -28,6 +28,7 @@
 #include "tail.h"
 #include "bufio.h"
 
+
 namespace ldq {
 
 // Lane i receives lane i - 1 (left neighbour column) / lane i + 1 (right)
@@ -369,6 +370,15 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
   pass_epilogue_n<NQ>(pref, tile, a.ntiles, q);
 }
 
+// Rows of a standard wave tile for stencil radius R: LDQ_ROWS2D rounded up to
+// a multiple of the five-row ring after the 4R halo rows.
+template <int R>
+constexpr int rows_full() {
+  int r = LDQ_ROWS2D;
+  while ((r + 4 * R) % 5 != 0) ++r;
+  return r;
+}
+
 // One tile of one probe: the march of the fused pass; q[] receives this
 // wave's sums of the pass's dot products.
 template <typename T, int R, bool OBS, int NG>
@@ -390,16 +400,11 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
   const int nrows = a.rows + 4 * R;
   const int ylo = y0 - 2 * R;
   const int degx = (x > 0) + (x < nx - 1);
-  const double c = a.kappa2 + 4.0;
-  const double m2c = -2.0 * c;
-  const double kd = NG > 0 ? a.kd + 4.0 : 0.0;
   const double gs0 = a.gs0;
   const double gs1 = a.gs1;
-  // A tile is interior when every column and every row it touches (prefetch
-  // included) has all four axis neighbours inside the lattice: no masking and
-  // a constant 13-point diagonal there.
-  const bool interior = a.rows == LDQ_ROWS2D && x0 - 2 * R >= 1 && x0 - 2 * R + 63 <= nx - 2 && ylo >= 1 &&
-                        ylo + nrows + 4 <= ny - 2;
+  // A tile is interior when every column and row it loads lies inside the
+  // lattice: no masking there.
+  const bool interior = x0 - 2 * R >= 0 && x0 - 2 * R + 63 <= nx - 1 && ylo >= 0 && ylo + nrows - 1 <= ny - 1;
 
   const int C = a.colC;
   const int cx = xin ? x % C : -1 - 2 * C;
@@ -433,58 +438,75 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
 #pragma unroll
   for (int i = 0; i < NQ; ++i) q[i] = 0.0;
 
+  // The operator is applied in the storage type T (FP32 in the mixed form,
+  // FP64 in the plain form) as M v = kappa2 v + (4 v - neighbours): the
+  // Laplacian's coefficients are exact in either type and only kappa2 is
+  // rounded, so the rows of M and M @ M keep their exact sums.  The squared
+  // operator runs two such stages, s = M (M p).  Dot products are FP64.
+  const T k2_t = (T)a.kappa2, dk_t = (T)(a.kd - a.kappa2), tau_t = (T)a.tau, alpha_t = (T)alpha;
+
   auto march = [&](auto interior_tag) {
     constexpr bool IN = decltype(interior_tag)::value;
-    const double cbase = c * c + (double)degx;       // 13-point diagonal without the row part
-    const double c0in = c * c + 4.0;
+    constexpr int NFULL = rows_full<R>() + 4 * R;
     int ay_g = row_part(ylo - 1);
     int ay_d = row_part(ylo - 2 * R);
     T qr[5], qp[5];
     auto fetch = [&](int slot, int i) {
-      const int yy = ylo + min(i, nrows - 1);
+      const int yy = ylo + min(i, NFULL - 1);
       const int yc = IN ? yy : min(max(yy, 0), ny - 1);
       qr[slot] = buf_ld((T *)nullptr, rs_rin, lx, (unsigned)yc * rowb);
       qp[slot] = buf_ld((T *)nullptr, rs_pin, lx, (unsigned)yc * rowb);
     };
 #pragma unroll
     for (int u = 0; u < 5; ++u) fetch(u, u);
-    double acc[5], acc2[5], obs_s[5], obs_r[5], macc[5];
+    // rings indexed by lattice row mod 5: t = M p and s = M t (or s = M p for
+    // the 5-point operator), tr = M r' and sr = M tr
+    T tacc[5], acc[5], tracc[5], acc2[5], obs_s[5], obs_r[5];
     T rq[5], pq[5], rnq[5], pl[5], pr[5], rl[5], rr[5];
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
-      acc[u] = acc2[u] = obs_s[u] = obs_r[u] = macc[u] = 0.0;
+      tacc[u] = acc[u] = tracc[u] = acc2[u] = obs_s[u] = obs_r[u] = T(0);
       rq[u] = pq[u] = rnq[u] = pl[u] = pr[u] = rl[u] = rr[u] = T(0);
     }
-    auto obs_row = [&](int yo, const T *lm, const T *cm, const T *rm, int um, int uc, int up) -> double {
+    // one 5-point stage: value v of row y arrives in slot u of ring m; row
+    // y - 1 of M v is complete afterwards and is returned
+    auto mstage = [&](T *m, int u, T v) -> T {
+      const T h = from_left(v) + from_right(v);
+      m[(u + 4) % 5] -= v;
+      m[u] += fma_t(k2_t, v, fma_t(T(4), v, -h));
+      const T done = m[(u + 4) % 5];
+      m[(u + 1) % 5] = -v;
+      return done;
+    };
+    auto obs_row = [&](int yo, const T *lm, const T *cm, const T *rm, int um, int uc, int up) -> T {
       // (A^T A v) of row yo with v rows held in the (l, c, r) rings at slots um, uc, up
       const int yoc = IN ? yo : min(max(yo, 0), ny - 1);
       const unsigned so = (unsigned)yoc * rowb;
-      const double v = (double)buf_ld((T *)nullptr, rs_obs, lx, so + 0u * vbytes) * (double)lm[um] +
-                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 1u * vbytes) * (double)cm[um] +
-                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 2u * vbytes) * (double)rm[um] +
-                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 3u * vbytes) * (double)lm[uc] +
-                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 4u * vbytes) * (double)cm[uc] +
-                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 5u * vbytes) * (double)rm[uc] +
-                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 6u * vbytes) * (double)lm[up] +
-                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 7u * vbytes) * (double)cm[up] +
-                       (double)buf_ld((T *)nullptr, rs_obs, lx, so + 8u * vbytes) * (double)rm[up];
-      return (IN || (yo >= 0 && yo < ny)) ? v : 0.0;
+      T v = buf_ld((T *)nullptr, rs_obs, lx, so + 0u * vbytes) * lm[um];
+      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 1u * vbytes), cm[um], v);
+      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 2u * vbytes), rm[um], v);
+      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 3u * vbytes), lm[uc], v);
+      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 4u * vbytes), cm[uc], v);
+      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 5u * vbytes), rm[uc], v);
+      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 6u * vbytes), lm[up], v);
+      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 7u * vbytes), cm[up], v);
+      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 8u * vbytes), rm[up], v);
+      return (IN || (yo >= 0 && yo < ny)) ? v : T(0);
     };
-    // Interior tiles of the standard height run the row loop fully unrolled:
-    // every prefetched value is then consumed in straight-line code and the
-    // compiler keeps the loads in flight (a loop back edge would force it to
-    // wait for them).
-    constexpr int NFULL = (IN ? LDQ_ROWS2D + 4 * R : 5);
-    const int nsteps = (IN && nrows == NFULL) ? NFULL : nrows;
+    // Interior tiles run the row loop fully unrolled (tiles have the standard
+    // height): every prefetched value is then consumed in straight-line code
+    // and the compiler keeps the loads in flight (a loop back edge would force
+    // it to wait for them).  Boundary tiles keep the loop: unrolled, their
+    // masking exhausts the registers.  (The row tests stay run-time branches:
+    // as compile-time constants they let the compiler stretch live ranges
+    // across the straight-line code, 85 -> 226 VGPRs.)
 #pragma unroll
-    for (int i0 = 0; i0 < (IN ? NFULL : nsteps); i0 += 5) {
+    for (int i0 = 0; i0 < (IN ? NFULL : nrows); i0 += 5) {
 #pragma unroll
       for (int u = 0; u < 5; ++u) {
         const int i = i0 + u;
         const int y = ylo + i;
-        // ---- row y arrives: p_k = r_k + beta p_{k-1} in the storage precision
-        // (p_k is stored rounded, so one correctly rounded fma matches the
-        // rounding the stored value carries anyway)
+        // ---- row y arrives: p_k = r_k + beta p_{k-1}
         T r_y = qr[u];
         T p_y = fma_t(beta_t, qp[u], qr[u]);
         if constexpr (!IN) {
@@ -495,48 +517,36 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
         fetch(u, i + 5);
         rq[u] = r_y;
         pq[u] = p_y;
-        const double p = p_y;
-        const T pL = from_left(p_y), pR = from_right(p_y);
-        const double h1 = (double)pL + (double)pR;
         if constexpr (OBS) {
-          pl[u] = pL;
-          pr[u] = pR;
+          pl[u] = from_left(p_y);
+          pr[u] = from_right(p_y);
         }
-        if constexpr (R == 2) {
-          const double h2 = (double)from_left(pL) + (double)from_right(pR);
-          const double c0 = IN ? c0in : cbase + (double)((y > 0) + (y < ny - 1));
-          const double t1 = __builtin_fma(m2c, p, h1 + h1);
-          acc[(u + 3) % 5] += p;
-          acc[(u + 4) % 5] += t1;
-          acc[u] += __builtin_fma(c0, p, __builtin_fma(m2c, h1, h2));
-          acc[(u + 1) % 5] += t1;
-          acc[(u + 2) % 5] = p;
-        } else {
-          acc[(u + 4) % 5] -= p;
-          acc[u] += __builtin_fma(c, p, -h1);
-          acc[(u + 1) % 5] = -p;
-        }
-        double ov = 0.0;                                              // (A^T A p) of row y - 1
+        // t = M p: row y - 1 complete; for the squared operator it enters the
+        // second stage, which completes row y - 2 of s = M t
+        T tv = mstage(tacc, u, p_y);
+        if constexpr (!IN) tv = (xin && y - 1 >= 0 && y - 1 < ny) ? tv : T(0);
+        if constexpr (R == 2) (void)mstage(acc, (u + 4) % 5, tv);
+        T ov = T(0);                                                  // (A^T A p) of row y - 1
         if constexpr (OBS) {
           ov = obs_row(y - 1, pl, pq, pr, (u + 3) % 5, (u + 4) % 5, u);
-          obs_s[(u + 4) % 5] = a.tau * ov;
+          obs_s[(u + 4) % 5] = tau_t * ov;
         }
         if constexpr (NG > 0) {
+          // (kd I + L) p = t + (kd - kappa2) p on row y - 1 over the probe's
+          // sites (scaled at the end)
           const int yg = y - 1;
           const bool gout = xout && yg >= y0 && yg < yb && mine_at(ay_g);
-          macc[(u + 4) % 5] -= p;                                     // (kappa_d^2 + L) p of row y - 1
-          q[LDQ_NQ_BASE] += gout ? gs0 * macc[(u + 4) % 5] : 0.0;
-          macc[u] += __builtin_fma(kd, p, -h1);
-          macc[(u + 1) % 5] = -p;
-          if constexpr (NG > 1 && OBS) q[LDQ_NQ_BASE + 1] += gout ? gs1 * ov : 0.0;
+          const T gv = fma_t(dk_t, pq[(u + 4) % 5], tv);
+          q[LDQ_NQ_BASE] += gout ? (double)gv : 0.0;
+          if constexpr (NG > 1 && OBS) q[LDQ_NQ_BASE + 1] += gout ? (double)ov : 0.0;
         }
         ay_g = advance(ay_g);
         // ---- row ys = y - R of s = Q p_k is complete: r_{k+1} = r_k - alpha s
         const int ys = y - R;
         const int us = (u + 5 - R) % 5;
-        double sv = acc[us];                                         // the fast path has scale 1
+        T sv = R == 2 ? acc[us] : tv;                                 // the fast path has scale 1
         if constexpr (OBS) sv += obs_s[us];
-        T rn = (T)__builtin_fma(-alpha, sv, (double)rq[us]);
+        T rn = fma_t(-alpha_t, sv, rq[us]);
         if constexpr (!IN) rn = (xin && ys >= 0 && ys < ny) ? rn : T(0);
         rnq[us] = rn;
         if (ys >= y0 && ys < yb) {
@@ -545,39 +555,26 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
             buf_st(pq[us], rs_pout, lx, (unsigned)ys * rowb);
           }
         }
-        // ---- row ys of r_{k+1} enters the Q r' accumulators
-        const double rv = rn;
-        const T rL = from_left(rn), rR = from_right(rn);
-        const double g1 = (double)rL + (double)rR;
+        // ---- row ys of r_{k+1} enters the Q r' stages
         if constexpr (OBS) {
-          rl[us] = rL;
-          rr[us] = rR;
+          rl[us] = from_left(rn);
+          rr[us] = from_right(rn);
         }
-        if constexpr (R == 2) {
-          const double g2 = (double)from_left(rL) + (double)from_right(rR);
-          const double c0 = IN ? c0in : cbase + (double)((ys > 0) + (ys < ny - 1));
-          const double t1 = __builtin_fma(m2c, rv, g1 + g1);
-          acc2[(us + 3) % 5] += rv;
-          acc2[(us + 4) % 5] += t1;
-          acc2[us] += __builtin_fma(c0, rv, __builtin_fma(m2c, g1, g2));
-          acc2[(us + 1) % 5] += t1;
-          acc2[(us + 2) % 5] = rv;
-        } else {
-          acc2[(us + 4) % 5] -= rv;
-          acc2[us] += __builtin_fma(c, rv, -g1);
-          acc2[(us + 1) % 5] = -rv;
-        }
+        T trv = mstage(tracc, us, rn);
+        if constexpr (!IN) trv = (xin && ys - 1 >= 0 && ys - 1 < ny) ? trv : T(0);
+        if constexpr (R == 2) (void)mstage(acc2, (us + 4) % 5, trv);
+        else acc2[(us + 4) % 5] = trv;
         if constexpr (OBS)
-          obs_r[(us + 4) % 5] = a.tau * obs_row(ys - 1, rl, rnq, rr, (us + 3) % 5, (us + 4) % 5, us);
-        // ---- row yd = ys - R of Q r_{k+1} is complete: dot products
+          obs_r[(us + 4) % 5] = tau_t * obs_row(ys - 1, rl, rnq, rr, (us + 3) % 5, (us + 4) % 5, us);
+        // ---- row yd = ys - R of Q r_{k+1} is complete: dot products (FP64)
         const int yd = ys - R;
         const int ud = (us + 5 - R) % 5;
         if (yd >= y0 && yd < yb) {
-          double qv = acc2[ud];
+          T qv = acc2[ud];
           if constexpr (OBS) qv += obs_r[ud];
           const double r2 = xout ? (double)rnq[ud] : 0.0;
           q[0] = __builtin_fma(r2, r2, q[0]);
-          q[1] = __builtin_fma(r2, qv, q[1]);
+          q[1] = __builtin_fma(r2, (double)qv, q[1]);
           q[2] += mine_at(ay_d) ? r2 : 0.0;
         }
         ay_d = advance(ay_d);
@@ -589,6 +586,8 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
     march(std::true_type{});
   else
     march(std::false_type{});
+  if constexpr (NG > 0) q[LDQ_NQ_BASE] *= gs0;
+  if constexpr (NG > 1) q[LDQ_NQ_BASE + 1] *= gs1;
 }
 
 // Batched STEP pass: one wave per work-list entry (field, probe, tile).
@@ -693,6 +692,8 @@ static void launch_gen(const Pass2D<T> &a, bool squared, bool obs, int nblocks, 
 template <typename T>
 hipError_t launch_pass2d(const Pass2D<T> &a, bool squared, bool obs, bool fast, hipStream_t stream) {
   const int nblocks = a.ntiles * a.nprobes;
+  // the fast pass assumes tiles of the standard height
+  fast = fast && a.rows == (squared ? rows_full<2>() : rows_full<1>());
   if (a.mode == MODE_STEP && fast) {
     const int ng = a.tail.ngrad;
     if (squared && obs) {
