@@ -406,9 +406,9 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
   // lattice: no masking there.
   const bool interior = x0 - 2 * R >= 0 && x0 - 2 * R + 63 <= nx - 1 && ylo >= 0 && ylo + nrows - 1 <= ny - 1;
 
-  const int C = a.colC;
+  const int C = __builtin_amdgcn_readfirstlane(a.colC);
   const int cx = xin ? x % C : -1 - 2 * C;
-  const int astep = a.cola % C;
+  const int astep = __builtin_amdgcn_readfirstlane(a.cola % C);   // uniform: scalar arithmetic below
   // (a y) mod C for y >= -5, uniform across the wave (kept in scalar registers)
   auto row_part = [&](int y) -> int {
     const int ym = ((y % C) + C) % C;
@@ -462,6 +462,9 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
     // rings indexed by lattice row mod 5: t = M p and s = M t (or s = M p for
     // the 5-point operator), tr = M r' and sr = M tr
     T tacc[5], acc[5], tracc[5], acc2[5], obs_s[5], obs_r[5];
+    // per-lane sums over the probe's sites (at most ceil(rows / C) terms):
+    // rho' and the gradient dots
+    T racc = T(0), gacc0 = T(0), gacc1 = T(0);
     T rq[5], pq[5], rnq[5], pl[5], pr[5], rl[5], rr[5];
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
@@ -535,10 +538,11 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
           // (kd I + L) p = t + (kd - kappa2) p on row y - 1 over the probe's
           // sites (scaled at the end)
           const int yg = y - 1;
-          const bool gout = xout && yg >= y0 && yg < yb && mine_at(ay_g);
-          const T gv = fma_t(dk_t, pq[(u + 4) % 5], tv);
-          q[LDQ_NQ_BASE] += gout ? (double)gv : 0.0;
-          if constexpr (NG > 1 && OBS) q[LDQ_NQ_BASE + 1] += gout ? (double)ov : 0.0;
+          if (yg >= y0 && yg < yb) {
+            const bool mine = mine_at(ay_g);
+            gacc0 += mine ? fma_t(dk_t, pq[(u + 4) % 5], tv) : T(0);
+            if constexpr (NG > 1 && OBS) gacc1 += mine ? ov : T(0);
+          }
         }
         ay_g = advance(ay_g);
         // ---- row ys = y - R of s = Q p_k is complete: r_{k+1} = r_k - alpha s
@@ -572,22 +576,26 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
         if (yd >= y0 && yd < yb) {
           T qv = acc2[ud];
           if constexpr (OBS) qv += obs_r[ud];
-          const double r2 = xout ? (double)rnq[ud] : 0.0;
+          const double r2 = (double)rnq[ud];
           q[0] = __builtin_fma(r2, r2, q[0]);
           q[1] = __builtin_fma(r2, (double)qv, q[1]);
-          q[2] += mine_at(ay_d) ? r2 : 0.0;
+          racc += mine_at(ay_d) ? rnq[ud] : T(0);
         }
         ay_d = advance(ay_d);
       }
     }
+    q[2] = (double)racc;
+    if constexpr (NG > 0) q[LDQ_NQ_BASE] = gs0 * (double)gacc0;
+    if constexpr (NG > 1) q[LDQ_NQ_BASE + 1] = gs1 * (double)gacc1;
     return true;
   };
   if (interior)
     march(std::true_type{});
   else
     march(std::false_type{});
-  if constexpr (NG > 0) q[LDQ_NQ_BASE] *= gs0;
-  if constexpr (NG > 1) q[LDQ_NQ_BASE + 1] *= gs1;
+  // lanes outside the strip's output columns computed halo values only
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) q[i] = xout ? q[i] : 0.0;
 }
 
 // Batched STEP pass: one wave per work-list entry (field, probe, tile).
