@@ -481,19 +481,33 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
       m[(u + 1) % 5] = -v;
       return done;
     };
-    auto obs_row = [&](int yo, const T *lm, const T *cm, const T *rm, int um, int uc, int up) -> T {
-      // (A^T A v) of row yo with v rows held in the (l, c, r) rings at slots um, uc, up
+    // A^T A planes of row y, loaded one step ahead at step y into slot u:
+    // used for p at step y + 1 (row y + 1 - 1) and for r' at step y + 3 (row
+    // ys - 1 = y)
+    T opl[5][9];
+#pragma unroll
+    for (int u = 0; u < 5; ++u)
+#pragma unroll
+      for (int d = 0; d < 9; ++d) opl[u][d] = T(0);
+    auto load_planes = [&](int slot, int yo) {
       const int yoc = IN ? yo : min(max(yo, 0), ny - 1);
       const unsigned so = (unsigned)yoc * rowb;
-      T v = buf_ld((T *)nullptr, rs_obs, lx, so + 0u * vbytes) * lm[um];
-      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 1u * vbytes), cm[um], v);
-      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 2u * vbytes), rm[um], v);
-      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 3u * vbytes), lm[uc], v);
-      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 4u * vbytes), cm[uc], v);
-      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 5u * vbytes), rm[uc], v);
-      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 6u * vbytes), lm[up], v);
-      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 7u * vbytes), cm[up], v);
-      v = fma_t(buf_ld((T *)nullptr, rs_obs, lx, so + 8u * vbytes), rm[up], v);
+#pragma unroll
+      for (int d = 0; d < 9; ++d) opl[slot][d] = buf_ld((T *)nullptr, rs_obs, lx, so + (unsigned)d * vbytes);
+    };
+    // (A^T A v) of row yo from the planes in `slot` and the v rows held in the
+    // (l, c, r) rings at slots um, uc, up
+    auto obs_row = [&](int slot, int yo, const T *lm, const T *cm, const T *rm, int um, int uc, int up) -> T {
+      const T *o = opl[slot];
+      T v = o[0] * lm[um];
+      v = fma_t(o[1], cm[um], v);
+      v = fma_t(o[2], rm[um], v);
+      v = fma_t(o[3], lm[uc], v);
+      v = fma_t(o[4], cm[uc], v);
+      v = fma_t(o[5], rm[uc], v);
+      v = fma_t(o[6], lm[up], v);
+      v = fma_t(o[7], cm[up], v);
+      v = fma_t(o[8], rm[up], v);
       return (IN || (yo >= 0 && yo < ny)) ? v : T(0);
     };
     // Interior tiles run the row loop fully unrolled (tiles have the standard
@@ -531,7 +545,8 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
         if constexpr (R == 2) (void)mstage(acc, (u + 4) % 5, tv);
         T ov = T(0);                                                  // (A^T A p) of row y - 1
         if constexpr (OBS) {
-          ov = obs_row(y - 1, pl, pq, pr, (u + 3) % 5, (u + 4) % 5, u);
+          load_planes(u, y);
+          ov = obs_row((u + 4) % 5, y - 1, pl, pq, pr, (u + 3) % 5, (u + 4) % 5, u);
           obs_s[(u + 4) % 5] = tau_t * ov;
         }
         if constexpr (NG > 0) {
@@ -569,7 +584,7 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
         if constexpr (R == 2) (void)mstage(acc2, (us + 4) % 5, trv);
         else acc2[(us + 4) % 5] = trv;
         if constexpr (OBS)
-          obs_r[(us + 4) % 5] = tau_t * obs_row(ys - 1, rl, rnq, rr, (us + 3) % 5, (us + 4) % 5, us);
+          obs_r[(us + 4) % 5] = tau_t * obs_row((u + 2) % 5, ys - 1, rl, rnq, rr, (us + 3) % 5, (us + 4) % 5, us);
         // ---- row yd = ys - R of Q r_{k+1} is complete: dot products (FP64)
         const int yd = ys - R;
         const int ud = (us + 5 - R) % 5;
