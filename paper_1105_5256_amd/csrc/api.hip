@@ -17,7 +17,7 @@
 namespace ldq {
 // launchers (pass2d.hip, pass3d.hip, misc.hip, colour.hip)
 template <typename T> hipError_t launch_pass2d(const Pass2D<T> &, bool, bool, bool, hipStream_t);
-template <typename T> hipError_t launch_pass3d(const Pass3D<T> &, hipStream_t);
+template <typename T> hipError_t launch_pass3d(const Pass3D<T> &, bool, hipStream_t);
 void pass2d_tiles(int nx, int ny, bool squared, int rows, int *tiles_x, int *ntiles);
 int pass2d_rows(bool squared, int want);
 void pass3d_tiles(int nx, int ny, int nz, int zseg, int *tiles_x, int *tiles_y, int *nzseg, int *ntiles);
@@ -967,7 +967,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   const bool is3d = Q->ndim == 3;
   // tiles
   int tiles_x = 0, tiles_y = 0, nzseg = 0, ntiles = 0;
-  const int zseg = 32;
+  const int zseg = 64;
   const int rows2d = pass2d_rows(Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN, LDQ_ROWS2D);
   if (is3d)
     pass3d_tiles((int)Q->shape[0], (int)Q->shape[1], (int)Q->shape[2], zseg, &tiles_x, &tiles_y, &nzseg, &ntiles);
@@ -1072,6 +1072,10 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     fast2d = fast2d && has_obs && grads[1].kind == GK_OBS && k.dQ[1]->obs_hash == Q->obs_hash &&
              k.dQ[1]->nobs == Q->nobs;
   if (P >= 2 && fast2d) a2.grad[1].scale = k.dQ[1]->tau;
+  // the specialised 3-D pass: modular colouring, scale 1, at most two diagonal
+  // derivative operators, 32-bit byte offsets
+  bool fast3d = is3d && !k.col.colours && Q->scale == 1.0 && P <= 2 && (double)Q->n * sizeof(T) < 4294967295.0;
+  for (int i = 0; i < P; ++i) fast3d = fast3d && grads[i].kind == GK_DIAG;
   // Launch with the probe state and partials read from buffer `in` and written to 1 - in.
   auto launch = [&](int mode, int nprobes, int in, const T *rin, const T *pin, T *rout, T *pout) -> hipError_t {
     TailArgs t = ta;
@@ -1088,7 +1092,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
       a3.p_in = pin;
       a3.r_out = rout;
       a3.p_out = pout;
-      return launch_pass3d<T>(a3, c->stream);
+      return launch_pass3d<T>(a3, fast3d, c->stream);
     }
     a2.mode = mode;
     a2.nprobes = nprobes;

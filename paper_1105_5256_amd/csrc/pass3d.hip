@@ -7,12 +7,17 @@
 // of r_{k+1} (xy halo 1) live in LDS as a rolling window, so every stored
 // vector element is read from HBM once per pass; only the xy halo and two
 // planes per segment are re-read (from L2).
+#include "bufio.h"
 #include "ldq_internal.h"
 #include "tail.h"
 
 namespace ldq {
 
-constexpr int T3X = 32, T3Y = 8;
+// Tile of one workgroup: T3X x T3Y output columns of the lattice (the fast
+// pass below puts one wave on each of the T3Y + 4 rows of the tile and its
+// halo, 64 = T3X + 4 lanes across), marched along z over zseg planes.
+constexpr int T3X = 60, T3Y = 12;
+constexpr int T3W = T3Y + 4;          // waves of the fast pass
 
 template <typename T>
 __device__ inline int colour3(const Pass3D<T> &a, int x, int y, int z) {
@@ -163,15 +168,271 @@ __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
   pass_epilogue<LDQ_BLOCK / 64>(a.tail, pref, tile, a.ntiles, q);
 }
 
+
+// Lane i receives lane i - 1 / i + 1 through a DPP wave shift (0 past the ends).
+__device__ inline float lane_left(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
+}
+__device__ inline float lane_right(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
+}
+__device__ inline double lane_left(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double lane_right(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+// Workgroup barrier for LDS traffic only: this wave's LDS accesses complete
+// (lgkmcnt 0; vmcnt and expcnt left at their maxima in the gfx9 encoding)
+// before it arrives, while its global loads stay in flight -- a full
+// __syncthreads would drain the prefetch at every step.  The empty asm
+// statements keep the compiler from moving memory accesses across.
+__device__ inline void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+__device__ inline float fma3(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma3(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Specialised STEP pass for modular colourings, Q = diag(kappa2) + L (a field
+// when FIELD, else a constant; scale 1) and NG diagonal derivative operators.
+// Wave w of the workgroup owns lattice row y0 - 2 + w, lane l column x0 - 2 +
+// l; z-neighbours are kept in registers (p at planes t - 1, t, t + 1; r' at
+// t - 2, t - 1, t), x-neighbours come from DPP lane shifts and y-neighbours
+// from one LDS row buffer per quantity, written once per z-step.  Step t forms
+// s = Q p_k and r_{k+1} = r_k - alpha s on plane t (waves 1 .. T3W - 2, so the
+// r' rows the next stencil needs exist) and Q r_{k+1} on plane t - 1 (the
+// output waves 2 .. T3W - 3); one barrier per step.  Loads run PF planes
+// ahead.  Arithmetic is in T with the Laplacian's exact coefficients; dot
+// products in FP64.
+template <typename T, int NG, bool FIELD>
+__global__ __launch_bounds__(64 * T3W) void pass3d_fast(Pass3D<T> a) {
+  constexpr int NQ = LDQ_NQ_BASE + NG;
+  constexpr int PF = 4;                       // prefetch distance in planes
+  __shared__ T sp[2][T3W][64];
+  __shared__ T srn[2][T3W][64];
+
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int probe = L / a.ntiles, tile = L - probe * a.ntiles;
+  const ProbeRef pref = probe_ref(a.tail, probe, a.ntiles);
+  const Step step = pass_prologue<T3W>(a.tail, pref, tile, a.ntiles, MODE_STEP);
+  if (!step.run) return;
+  const int colour = __builtin_amdgcn_readfirstlane(step.colour);
+  const T alpha_t = (T)step.alpha, beta_t = (T)step.beta;
+
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int txi = tile % a.tiles_x, rest = tile / a.tiles_x;
+  const int tyi = rest % a.tiles_y, tzi = rest / a.tiles_y;
+  const int x0 = txi * T3X, y0 = tyi * T3Y, z0 = tzi * a.zseg;
+  const int z1 = min(z0 + a.zseg, nz);
+  const int x = x0 - 2 + lane, y = y0 - 2 + w;
+  const bool xin = x >= 0 && x < nx, yin = y >= 0 && y < ny;
+  const bool in = xin && yin;
+  const bool own = lane >= 2 && lane < 62 && x < nx && w >= 2 && w < T3W - 2 && y < ny;
+  const int xc = min(max(x, 0), nx - 1), yc = min(max(y, 0), ny - 1);
+
+  const size_t n = (size_t)nx * ny * nz;
+  const size_t off = (size_t)probe * n;
+  const unsigned vbytes = (unsigned)(n * sizeof(T));
+  const __amdgpu_buffer_rsrc_t rs_rin = make_rsrc(a.r_in + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_pin = make_rsrc(a.p_in + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_rout = make_rsrc(a.r_out + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_pout = make_rsrc(a.p_out + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_k2 = make_rsrc(FIELD ? a.kappa2_field : a.r_in, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_g0 = make_rsrc(NG > 0 ? a.grad[0].field : a.r_in, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_g1 = make_rsrc(NG > 1 ? a.grad[1].field : a.r_in, vbytes);
+  const unsigned lo = ((unsigned)yc * (unsigned)nx + (unsigned)xc) * (unsigned)sizeof(T);   // lane offset in a plane
+  const unsigned planeb = (unsigned)nx * (unsigned)ny * (unsigned)sizeof(T);
+  const T k2c = (T)a.kappa2;
+  const T g0s = NG > 0 ? (T)a.grad[0].scale : T(0), g1s = NG > 1 ? (T)a.grad[1].scale : T(0);
+
+  // colour (x + a y + b z) mod C == j  <=>  x mod C == (j - a y - b z) mod C
+  const int C = __builtin_amdgcn_readfirstlane(a.colC);
+  const int cx = xin ? x % C : -1;
+  const int ay = __builtin_amdgcn_readfirstlane((int)(((long)a.cola * ((y % C + C) % C)) % C));
+  const int bstep = __builtin_amdgcn_readfirstlane(a.colb % C);
+  auto bz_of = [&](int z) -> int {
+    return __builtin_amdgcn_readfirstlane((int)(((long)bstep * ((z % C + C) % C)) % C));
+  };
+  auto bz_next = [&](int bz) -> int {
+    bz += bstep;
+    return __builtin_amdgcn_readfirstlane(bz >= C ? bz - C : bz);
+  };
+  auto mine = [&](int bz) -> bool {
+    int t = colour - ay - bz;
+    t += (t < 0) ? C : 0;
+    t += (t < 0) ? C : 0;
+    return cx == t;
+  };
+
+  // prefetch ring: the raw r and p_{k-1} loads of plane z sit in slot
+  // (z - zs) mod (PF + 1), zs = z0 - 2 the first plane of the march
+  // together with kappa2 and, on the probe's own sites, the derivative
+  // diagonals (every load of a step is issued PF planes ahead: waits are in
+  // issue order, so one late load would drain the whole prefetch)
+  T fr[PF + 1], fp[PF + 1], fk[PF + 1], fg0[PF + 1], fg1[PF + 1];
+  auto load_into = [&](int k, int z, int bz) {
+    const int zc = min(max(z, 0), nz - 1);
+    const unsigned so = (unsigned)zc * planeb;
+    fr[k] = buf_ld((T *)nullptr, rs_rin, lo, so);
+    fp[k] = buf_ld((T *)nullptr, rs_pin, lo, so);
+    if constexpr (FIELD) fk[k] = buf_ld((T *)nullptr, rs_k2, lo, so);
+    if constexpr (NG > 0) {
+      // only the probe's own sites read memory: the other lanes address past
+      // the end of the buffer, which the hardware range check answers with 0
+      // (an unconditional load keeps the wait counting in issue order)
+      const bool use = own && z >= z0 && z < z1 && mine(bz);
+      const unsigned go = use ? lo + so : 0xFFFFFFF0u;
+      fg0[k] = buf_ld((T *)nullptr, rs_g0, go, 0u);
+      if constexpr (NG > 1) fg1[k] = buf_ld((T *)nullptr, rs_g1, go, 0u);
+    }
+  };
+
+  // p_k of plane z from its raw loads (0 outside the lattice)
+  auto form_p = [&](T r, T pv, int z) -> T {
+    const bool ok = in && z >= 0 && z < nz;
+    return ok ? fma3(beta_t, pv, r) : T(0);
+  };
+
+  double q0 = 0.0, q1 = 0.0;
+  T racc = T(0), g0acc = T(0), g1acc = T(0);
+
+  // start: planes zs .. zs + PF in the ring; slots 0 and 1 are consumed at
+  // once and refilled with planes zs + PF + 1 and zs + PF + 2
+  const int zs = z0 - 2;
+  // colour part of the planes: bz_l of the next plane to load
+  int bz_l = bz_of(zs);
+#pragma unroll
+  for (int k = 0; k <= PF; ++k) {
+    load_into(k, zs + k, bz_l);
+    bz_l = bz_next(bz_l);
+  }
+  // rings: p at t - 1, t, t + 1; r at t; r' at t - 2, t - 1; kappa2 at t - 1, t
+  T pm = form_p(fr[0], fp[0], zs), pc = form_p(fr[1], fp[1], zs + 1);
+  T rc = (in && zs + 1 >= 0 && zs + 1 < nz) ? fr[1] : T(0);
+  T kc = FIELD ? fk[1] : k2c, km = T(0);
+  T g0c = fg0[1], g1c = fg1[1];
+  load_into(0, zs + PF + 1, bz_l);
+  bz_l = bz_next(bz_l);
+  load_into(1, zs + PF + 2, bz_l);
+  bz_l = bz_next(bz_l);
+  T rnm2 = T(0), rnm1 = T(0);
+  int bz_m = bz_of(zs);          // colour part of plane t - 1 (t = zs + 1 at the first step)
+
+  // the ring slot of plane z is (z - zs) mod (PF + 1); the loop is unrolled by
+  // PF + 1 so slots are compile-time
+  const int nsteps = z1 - zs;    // steps t = zs + 1 .. z1
+  for (int b = 0; b < nsteps; b += PF + 1) {
+#pragma unroll
+    for (int u = 0; u < PF + 1; ++u) {
+      const int i = b + u;
+      if (i >= nsteps) break;
+      const int t = zs + 1 + i;
+      // plane t + 1 of p from the ring, then refill its slot with plane t + 1 + PF
+      const int sn = (u + 2) % (PF + 1);
+      const T rn1 = fr[sn], pn1raw = fp[sn];
+      const T pp = form_p(rn1, pn1raw, t + 1);
+      const T kn = FIELD ? ((in && t + 1 >= 0 && t + 1 < nz) ? fk[sn] : T(0)) : k2c;
+      const T g0n = fg0[sn], g1n = fg1[sn];
+      load_into(sn, t + PF + 2, bz_l);
+      bz_l = bz_next(bz_l);
+      const bool tin = t >= 0 && t < nz;
+      // y-neighbours of p_k on plane t
+      sp[t & 1][w][lane] = pc;
+      lds_barrier();
+      T s = T(0);
+      const T ks = FIELD ? kc : k2c;
+      {
+        const T up = (w > 0) ? sp[t & 1][w - 1][lane] : T(0);
+        const T dn = (w < T3W - 1) ? sp[t & 1][w + 1][lane] : T(0);
+        const T nb = (lane_left(pc) + lane_right(pc)) + (up + dn) + (pm + pp);
+        s = fma3(ks, pc, fma3(T(6), pc, -nb));
+      }
+      const T rnew = (in && tin) ? fma3(-alpha_t, s, rc) : T(0);
+      const int bz_c = bz_next(bz_m);
+      if (own && t >= z0 && t < z1) {
+        const unsigned so = (unsigned)t * planeb;
+        buf_st(rnew, rs_rout, lo, so);
+        buf_st(pc, rs_pout, lo, so);
+        if constexpr (NG > 0) {
+          // the diagonals were loaded (PF planes ago) on the probe's sites only
+          g0acc = fma3(g0c, pc, g0acc);
+          if constexpr (NG > 1) g1acc = fma3(g1c, pc, g1acc);
+        }
+      }
+      srn[t & 1][w][lane] = rnew;
+      // Q r_{k+1} on plane t - 1 (its y-neighbours were written last step)
+      if (t - 1 >= z0 && t - 1 < z1) {
+        const T up = (w > 0) ? srn[(t - 1) & 1][w - 1][lane] : T(0);
+        const T dn = (w < T3W - 1) ? srn[(t - 1) & 1][w + 1][lane] : T(0);
+        const T nb = (lane_left(rnm1) + lane_right(rnm1)) + (up + dn) + (rnm2 + rnew);
+        const T km_t = FIELD ? km : k2c;
+        const T qr = fma3(km_t, rnm1, fma3(T(6), rnm1, -nb));
+        const double r2 = (double)rnm1;
+        q0 = __builtin_fma(r2, r2, q0);
+        q1 = __builtin_fma(r2, (double)qr, q1);
+        racc += mine(bz_m) ? rnm1 : T(0);
+      }
+      // rotate
+      pm = pc;
+      pc = pp;
+      rc = (in && t + 1 >= 0 && t + 1 < nz) ? rn1 : T(0);
+      rnm2 = rnm1;
+      rnm1 = rnew;
+      km = kc;
+      kc = kn;
+      g0c = g0n;
+      g1c = g1n;
+      bz_m = bz_c;
+    }
+  }
+  double qv[NQ];
+  qv[0] = own ? q0 : 0.0;
+  qv[1] = own ? q1 : 0.0;
+  qv[2] = own ? (double)racc : 0.0;
+  if constexpr (NG > 0) qv[LDQ_NQ_BASE] = own ? (double)g0s * (double)g0acc : 0.0;
+  if constexpr (NG > 1) qv[LDQ_NQ_BASE + 1] = own ? (double)g1s * (double)g1acc : 0.0;
+  double tot[LDQ_NQ_MAX];
+#pragma unroll
+  for (int i = 0; i < LDQ_NQ_MAX; ++i) tot[i] = i < NQ ? qv[i] : 0.0;
+  pass_epilogue<T3W>(a.tail, pref, tile, a.ntiles, tot);
+}
+
+// fast: STEP pass with a modular colouring, scale 1 and at most two diagonal
+// derivative operators (checked by the host driver)
 template <typename T>
-hipError_t launch_pass3d(const Pass3D<T> &a, hipStream_t stream) {
+hipError_t launch_pass3d(const Pass3D<T> &a, bool fast, hipStream_t stream) {
   const int nblocks = a.ntiles * a.nprobes;
-  hipLaunchKernelGGL((pass3d_kernel<T>), dim3(nblocks), dim3(LDQ_BLOCK), 0, stream, a);
+  if (fast && a.mode == MODE_STEP) {
+    const bool field = a.kappa2_field != nullptr;
+    const dim3 g(nblocks), b(64 * T3W);
+    switch (a.tail.ngrad * 2 + (field ? 1 : 0)) {
+      case 0: hipLaunchKernelGGL((pass3d_fast<T, 0, false>), g, b, 0, stream, a); break;
+      case 1: hipLaunchKernelGGL((pass3d_fast<T, 0, true>), g, b, 0, stream, a); break;
+      case 2: hipLaunchKernelGGL((pass3d_fast<T, 1, false>), g, b, 0, stream, a); break;
+      case 3: hipLaunchKernelGGL((pass3d_fast<T, 1, true>), g, b, 0, stream, a); break;
+      case 4: hipLaunchKernelGGL((pass3d_fast<T, 2, false>), g, b, 0, stream, a); break;
+      default: hipLaunchKernelGGL((pass3d_fast<T, 2, true>), g, b, 0, stream, a); break;
+    }
+  } else {
+    hipLaunchKernelGGL((pass3d_kernel<T>), dim3(nblocks), dim3(LDQ_BLOCK), 0, stream, a);
+  }
   return hipGetLastError();
 }
 
-template hipError_t launch_pass3d<float>(const Pass3D<float> &, hipStream_t);
-template hipError_t launch_pass3d<double>(const Pass3D<double> &, hipStream_t);
+template hipError_t launch_pass3d<float>(const Pass3D<float> &, bool, hipStream_t);
+template hipError_t launch_pass3d<double>(const Pass3D<double> &, bool, hipStream_t);
 
 void pass3d_tiles(int nx, int ny, int nz, int zseg, int *tiles_x, int *tiles_y, int *nzseg, int *ntiles) {
   *tiles_x = (nx + T3X - 1) / T3X;
