@@ -133,6 +133,8 @@ struct ldq_ctx {
   DevBuf vec, partials, pstate, sstate, shifts, classes, terms, stats, sums, misc, colbuf, jpkey, jpmask, hist;
   DevBuf bfields, bitems, bwork;   // batched lattice passes
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evp[2] = {nullptr, nullptr};   // convergence polls
+  int *hpin = nullptr;                      // pinned host copies of the device counters
   std::vector<double> last_terms;
   int last_nparams = 0;
   int64_t last_count = 0;
@@ -167,6 +169,9 @@ struct ldq_op {
   uint64_t serial = 0;         // identifies the operator in caches keyed by operators
   double est_lo = 0.0, est_hi = 0.0;   // estimated enclosure of a CSR operator
   bool est_ok = false;
+  // non-empty colour classes of the last modular colouring (C, a, b)
+  int cls_C = 0, cls_a = 0, cls_b = 0;
+  std::vector<int32_t> cls;
   struct Slab *slab = nullptr; // sliced layout of a CSR Q with its derivative operators
 };
 
@@ -210,9 +215,11 @@ extern "C" int ldq_create(int device, void *hip_stream, ldq_ctx **out) {
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   if (hipSetDevice(device) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
-      hipEventCreate(&c->ev1) != hipSuccess) {
-    delete c;
-    return fail(LDQ_E_DEVICE, "hipSetDevice/hipEventCreate failed");
+      hipEventCreate(&c->ev1) != hipSuccess || hipEventCreate(&c->evp[0]) != hipSuccess ||
+      hipEventCreate(&c->evp[1]) != hipSuccess || hipHostMalloc((void **)&c->hpin, 16 * sizeof(int)) != hipSuccess) {
+    (void)hipGetLastError();
+    ldq_destroy(c);
+    return fail(LDQ_E_DEVICE, "hipSetDevice/hipEventCreate/hipHostMalloc failed");
   }
   *out = c;
   return LDQ_OK;
@@ -228,6 +235,9 @@ extern "C" void ldq_destroy(ldq_ctx *c) {
     b->release();
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->evp)
+    if (e) hipEventDestroy(e);
+  if (c->hpin) hipHostFree(c->hpin);
   delete c;
 }
 
@@ -911,6 +921,36 @@ static void lanczos_extremes(const double *h, int K, double *tmin, double *tmax)
   *tmax = bisect(K);
 }
 
+// Queue chunks of launches until the device counter `active` reads 0.  The
+// count after chunk c is copied to pinned host memory behind the chunk, and
+// the host waits for it only after queueing chunk c + 1, so the device does
+// not idle while the host decides; the extra chunk finds every probe stopped
+// and its launches return at once.  *stalled when max_chunks are exceeded.
+template <typename F>
+static int poll_chunks(ldq_ctx *c, const int *active, F enqueue_chunk, int64_t max_chunks, int64_t *chunks,
+                       bool *stalled) {
+  int slot = 0, pending = -1;
+  *chunks = 0;
+  *stalled = false;
+  for (;;) {
+    CHK(enqueue_chunk());
+    ++*chunks;
+    HIPCHK(hipMemcpyAsync(c->hpin + slot, active, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipEventRecord(c->evp[slot], c->stream));
+    if (pending >= 0) {
+      HIPCHK(hipEventSynchronize(c->evp[pending]));
+      if (c->hpin[pending] == 0) break;
+    }
+    pending = slot;
+    slot ^= 1;
+    if (*chunks > max_chunks) {
+      *stalled = true;
+      break;
+    }
+  }
+  return LDQ_OK;
+}
+
 // Reduce the per-probe terms in probe order, bring the sums, the statistics
 // and the terms to the host and fill the common fields of info.
 static int collect_results(Call &k, int nprobes_total, double kernel_ms, int64_t passes, ldq_info *info,
@@ -1122,11 +1162,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     HIPCHK(launch(MODE_FIRST, nb, 0, nullptr, nullptr, bufA_r, bufA_p));
     passes += 2;
     bool in_a = true;
-    int h_active = nb;
-    int64_t steps = 0;
-    bool chunk_open = true;
-    while (h_active > 0) {
-      if (!chunk_open) HIPCHK(hipEventRecord(c->ev0, c->stream));
+    auto chunk = [&]() -> int {
       for (int i = 0; i < check; ++i) {
         if (in_a)
           HIPCHK(launch(MODE_STEP, nb, 1, bufA_r, bufA_p, bufB_r, bufB_p));
@@ -1134,20 +1170,18 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
           HIPCHK(launch(MODE_STEP, nb, 0, bufB_r, bufB_p, bufA_r, bufA_p));
         in_a = !in_a;
       }
-      HIPCHK(hipEventRecord(c->ev1, c->stream));
-      chunk_open = false;
-      passes += check;
-      steps += check;
-      HIPCHK(hipMemcpyAsync(&h_active, active_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(hipStreamSynchronize(c->stream));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-      kernel_ms += ms;
-      if (steps > (int64_t)k.o.max_iter + 2 * check) {
-        stalled = true;
-        break;
-      }
-    }
+      return LDQ_OK;
+    };
+    int64_t chunks = 0;
+    bool st_block = false;
+    CHK(poll_chunks(c, active_count, chunk, ((int64_t)k.o.max_iter + 2 * check) / check + 1, &chunks, &st_block));
+    passes += chunks * check;
+    stalled = stalled || st_block;
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    HIPCHK(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    kernel_ms += ms;
     HIPCHK(launch_lanczos_check(ta.hist, st[1], nb, hcap, clo, chi, c->stats.as<int>(), c->stream));
     HIPCHK(launch_probe_terms(st[1], ta.sh, dcoef, nb, N, P, c->terms.as<double>(), first, c->stats.as<int>(),
                               c->stream));
@@ -1436,11 +1470,7 @@ static int run_krylov_csr(Call &k, ldq_info *info, double *out_sums) {
       HIPCHK(launch_csr_pass_b<T>(a, W, false, c->stream));
       passes += 1;
       bool in_a = true;
-      int h_active = nb;
-      int64_t steps = 0;
-      bool chunk_open = true;
-      while (h_active > 0) {
-        if (!chunk_open) HIPCHK(hipEventRecord(c->ev0, c->stream));
+      auto chunk = [&]() -> int {
         for (int i = 0; i < check; ++i) {
           HIPCHK(launch_csr_tail(ta, nb, ntiles, MODE_STEP, c->stream));
           a.r_in = in_a ? bufA_r : bufB_r;
@@ -1452,20 +1482,19 @@ static int run_krylov_csr(Call &k, ldq_info *info, double *out_sums) {
           HIPCHK(launch_csr_pass_b<T>(a, W, false, c->stream));
           in_a = !in_a;
         }
-        HIPCHK(hipEventRecord(c->ev1, c->stream));
-        chunk_open = false;
-        passes += check;
-        steps += check;
-        HIPCHK(hipMemcpyAsync(&h_active, active_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-        kernel_ms += ms;
-        if (steps > (int64_t)k.o.max_iter + 2 * check) {
-          stalled = true;
-          break;
-        }
-      }
+        return LDQ_OK;
+      };
+      int64_t chunks = 0;
+      bool st_block = false;
+      CHK(poll_chunks(c, active_count, chunk, ((int64_t)k.o.max_iter + 2 * check) / check + 1, &chunks,
+                      &st_block));
+      passes += chunks * check;
+      stalled = stalled || st_block;
+      HIPCHK(hipEventRecord(c->ev1, c->stream));
+      HIPCHK(hipEventSynchronize(c->ev1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      kernel_ms += ms;
       HIPCHK(launch_lanczos_check(ta.hist, st, nb, hcap, clo, chi, c->stats.as<int>(), c->stream));
       if (k.estimated && attempt < 3) {
         int viol = 0;
@@ -1571,9 +1600,13 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
     k.dQ[i] = const_cast<ldq_op *>(dQ[i]);
   }
   CHK(set_device(c));
-  // a1: colouring and its non-empty classes
+  // a1: colouring and its non-empty classes (a modular colouring's classes
+  // are kept on the operator)
   CHK(resolve_colouring(c, Q, k.o.k, k.o.colouring, k.o.user_colours, k.o.priority, &k.col));
-  {
+  const bool modular = !k.col.colours;
+  if (modular && Q->cls_C == k.col.C && Q->cls_a == k.col.a && Q->cls_b == k.col.b && !Q->cls.empty()) {
+    k.classes = Q->cls;
+  } else {
     const int C = k.col.ncolours;
     DevBuf cnt;
     CHK(cnt.reserve((size_t)C * sizeof(int)));
@@ -1593,6 +1626,13 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
     k.classes.clear();
     for (int j = 0; j < C; ++j)
       if (h[j] > 0) k.classes.push_back(j);
+    if (modular) {
+      ldq_op *Qm = k.Q;
+      Qm->cls = k.classes;
+      Qm->cls_C = k.col.C;
+      Qm->cls_a = k.col.a;
+      Qm->cls_b = k.col.b;
+    }
   }
   // a2: enclosure
   if (k.o.lambda_min > 0.0 && k.o.lambda_max > 0.0) {

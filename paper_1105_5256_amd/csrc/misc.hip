@@ -213,16 +213,28 @@ hipError_t launch_modular_fill(int32_t *col, int nx, int ny, int nz, int C, int 
   return hipGetLastError();
 }
 
-// Count of sites per colour (integer atomics: order-independent).
+// Count of sites per colour (integer atomics: order-independent).  Up to
+// 4096 colours are counted in a per-workgroup LDS histogram first, so the
+// global counters see one atomic per colour and workgroup.
+constexpr int LDQ_HIST = 4096;
 __global__ void class_count_kernel(const int32_t *col, size_t n, int C, int *count) {
+  __shared__ int hist[LDQ_HIST];
+  const bool local = C <= LDQ_HIST;
+  if (local)
+    for (int c = threadIdx.x; c < C; c += blockDim.x) hist[c] = 0;
+  __syncthreads();
   for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (size_t)gridDim.x * blockDim.x) {
     const int c = col[s];
-    if (c >= 0 && c < C) atomicAdd(count + c, 1);
+    if (c >= 0 && c < C) atomicAdd(local ? hist + c : count + c, 1);
   }
+  __syncthreads();
+  if (local)
+    for (int c = threadIdx.x; c < C; c += blockDim.x)
+      if (hist[c]) atomicAdd(count + c, hist[c]);
 }
 
 hipError_t launch_class_count(const int32_t *col, size_t n, int C, int *count, hipStream_t s) {
-  const int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
   hipLaunchKernelGGL(class_count_kernel, dim3(blocks), dim3(256), 0, s, col, n, C, count);
   return hipGetLastError();
 }
