@@ -7,21 +7,26 @@
 //   r_{k+1} = r_k - alpha s
 //   gamma' = r'.r', delta' = r'.Q r', rho' = sum_{c(x) = j} r'(x)
 // storing r_{k+1} and p_k: with FP32 storage, 16 B per site, the minimum for
-// reading and writing r and p once.  Arithmetic is FP64 throughout.
+// reading and writing r and p once.
 //
-// Work decomposition ("wave march"): one wave64 owns a strip of W = 64 - 4R
-// lattice columns (R = stencil radius: 1 for the 5-point M, 2 for M @ M) and
-// `rows` rows.  Lane l holds column x0 - 2R + l; the wave walks down the rows
-// y0 - 2R .. y0 + rows + 2R - 1, loading one row of r and p per step
-// (prefetched five rows ahead), and assembles Q p row by row: the contribution
-// of an arriving row to the stencil sums of the rows within distance R is
-// added to a ring of per-row accumulators held in registers; horizontal
-// neighbours come from DPP lane shifts.  A row of s is complete R steps after
-// it arrives, a row of Q r' another R steps later.  Waves are independent: no
-// LDS and no workgroup barriers.  Dot products are reduced per wave and written
-// as one partial per (probe, quantity, wave tile); the next launch reduces them
-// (tail.h).  rows + 4R is a multiple of 5 (the ring length), so the unrolled
-// row loop needs no bounds check.
+// Q is scale * M (5-point, R = 1) or scale * M @ M (13-point, R = 2), M =
+// kappa2 I + L symmetric, plus optionally tau A^T A.  delta' needs M r' on the
+// tile's own sites only: r'.M r' for R = 1 and |M r'|^2 for R = 2 (M
+// symmetric), so the halo around a tile is H = R + 1 sites (r' on the own
+// sites +- 1, hence s there, hence p on +- (R + 1)).
+//
+// Work decomposition ("wave march"): one wave64 owns a strip of W = 64 - 2H
+// lattice columns and `rows` rows.  Lane l holds column x0 - H + l; the wave
+// walks down the rows y0 - H .. y0 + rows + H - 1, loading one row of r and p
+// per step (prefetched five rows ahead), and assembles Q p row by row: the
+// contribution of an arriving row to the stencil sums of the rows within
+// distance R is added to a ring of per-row accumulators held in registers;
+// horizontal neighbours come from DPP lane shifts.  A row of s is complete R
+// steps after it arrives, a row of M r' one step later.  Waves are
+// independent: no LDS and no workgroup barriers.  Dot products are reduced per
+// wave and written as one partial per (probe, quantity, wave tile); the next
+// launch reduces them (tail.h).  rows + 2H is a multiple of 5 (the ring
+// length), so the unrolled row loop needs no bounds check.
 #include <type_traits>
 
 #include "ldq_internal.h"
@@ -71,7 +76,8 @@ __device__ inline double obs_apply(const T *o, size_t n, size_t so, T lm, T cm, 
 
 template <typename T, int R, bool OBS, int NG, bool GEN>
 __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
-  constexpr int W = 64 - 4 * R;
+  constexpr int H = R + 1;
+  constexpr int W = 64 - 2 * H;
   constexpr int NQ = LDQ_NQ_BASE + NG;
   const int lane = threadIdx.x;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -91,12 +97,12 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int x0 = tx * W, y0 = ty * a.rows;
   const int yb = min(y0 + a.rows, ny);
-  const int x = x0 - 2 * R + lane;
+  const int x = x0 - H + lane;
   const int xc = min(max(x, 0), nx - 1);           // clamped column: every load address is valid
   const bool xin = x >= 0 && x < nx;
-  const bool xout = lane >= 2 * R && lane < 64 - 2 * R && x < nx;   // output column of this strip
-  const int nrows = a.rows + 4 * R;                // multiple of 5
-  const int ylo = y0 - 2 * R;                      // lattice row of step 0
+  const bool xout = lane >= H && lane < 64 - H && x < nx;   // output column of this strip
+  const int nrows = a.rows + 2 * H;                // multiple of 5
+  const int ylo = y0 - H;                          // lattice row of step 0
   const int degx = (x > 0) + (x < nx - 1);
   const double c = a.kappa2 + 4.0;                 // M = (kappa2 + 4) I - (axis neighbours)
 
@@ -124,7 +130,7 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
   };
   int ay_in = row_part(ylo);                       // row part of the arriving row
   int ay_g = row_part(ylo - 1);                    // ... of the gradient row y - 1
-  int ay_d = row_part(ylo - 2 * R);                // ... of the dot-product row y - 2R
+  int ay_d = row_part(ylo - R - 1);                // ... of the dot-product row y - R - 1
 
   const T *rin = a.r_in + off + xc;
   const T *pin = a.p_in + off + xc;
@@ -265,7 +271,7 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
         rout[o] = rn;
         pout[o] = pq[us];
       }
-      // ---- row ys of r_{k+1} enters the Q r' accumulators
+      // ---- row ys of r_{k+1} enters the M r' ring: row ys - 1 of M r' is complete
       const double rv = rn;
       const T rL = from_left(rn), rR = from_right(rn);
       const double g1 = (double)rL + (double)rR;
@@ -273,20 +279,9 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
         rl[us] = rL;
         rr[us] = rR;
       }
-      if constexpr (R == 2) {
-        const double g2 = (double)from_left(rL) + (double)from_right(rR);
-        const double c0 = c * c + (double)(degx + (ys > 0) + (ys < ny - 1));
-        const double t1 = 2.0 * g1 - 2.0 * c * rv;
-        acc2[(us + 3) % 5] += rv;                                   // row ys - 2 complete
-        acc2[(us + 4) % 5] += t1;
-        acc2[us] += c0 * rv - 2.0 * c * g1 + g2;
-        acc2[(us + 1) % 5] += t1;
-        acc2[(us + 2) % 5] = rv;
-      } else {
-        acc2[(us + 4) % 5] -= rv;                                   // row ys - 1 complete
-        acc2[us] += (k2q[us] + 4.0) * rv - g1;
-        acc2[(us + 1) % 5] = -rv;
-      }
+      acc2[(us + 4) % 5] -= rv;
+      acc2[us] += ((R == 1 ? k2q[us] : a.kappa2) + 4.0) * rv - g1;
+      acc2[(us + 1) % 5] = -rv;
       if constexpr (OBS) {
         const int yo = ys - 1;
         double v = 0.0;
@@ -297,16 +292,18 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
         }
         obs_r[(us + 4) % 5] = a.tau * v;
       }
-      // ---- row yd = ys - R of Q r_{k+1} is complete: dot products
-      const int yd = ys - R;
-      const int ud = (us + 5 - R) % 5;
+      // ---- dot products on row yd = ys - 1: r'.Q r' = scale r'.M r' (R = 1)
+      // or scale |M r'|^2 (R = 2), plus r'.tau A^T A r'
+      const int yd = ys - 1;
+      const int ud = (us + 4) % 5;
       {
         const bool dout = xout && yd >= y0 && yd < yb;
-        double qv = a.scale * acc2[ud];
-        if constexpr (OBS) qv += obs_r[ud];
         const double r2 = dout ? (double)rnq[ud] : 0.0;
+        const double mr = dout ? acc2[ud] : 0.0;
+        double qv = a.scale * mr * (R == 2 ? mr : r2);
+        if constexpr (OBS) qv += r2 * obs_r[ud];
         q[0] += r2 * r2;
-        q[1] += r2 * qv;
+        q[1] += qv;
         q[2] += (dout && mine_at(yd, ay_d)) ? r2 : 0.0;
       }
       ay_d = advance(ay_d);
@@ -371,11 +368,11 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
 }
 
 // Rows of a standard wave tile for stencil radius R: LDQ_ROWS2D rounded up to
-// a multiple of the five-row ring after the 4R halo rows.
+// a multiple of the five-row ring after the 2H = 2R + 2 halo rows.
 template <int R>
 constexpr int rows_full() {
   int r = LDQ_ROWS2D;
-  while ((r + 4 * R) % 5 != 0) ++r;
+  while ((r + 2 * R + 2) % 5 != 0) ++r;
   return r;
 }
 
@@ -383,7 +380,8 @@ constexpr int rows_full() {
 // wave's sums of the pass's dot products.
 template <typename T, int R, bool OBS, int NG>
 __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, double alpha, double beta, double *q) {
-  constexpr int W = 64 - 4 * R;
+  constexpr int H = R + 1;
+  constexpr int W = 64 - 2 * H;
   constexpr int NQ = LDQ_NQ_BASE + NG;
   const int lane = threadIdx.x & 63;
   const T beta_t = (T)beta;
@@ -393,37 +391,24 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int x0 = tx * W, y0 = ty * a.rows;
   const int yb = min(y0 + a.rows, ny);
-  const int x = x0 - 2 * R + lane;
+  const int x = x0 - H + lane;
   const int xc = min(max(x, 0), nx - 1);
   const bool xin = x >= 0 && x < nx;
-  const bool xout = lane >= 2 * R && lane < 64 - 2 * R && x < nx;
-  const int nrows = a.rows + 4 * R;
-  const int ylo = y0 - 2 * R;
-  const int degx = (x > 0) + (x < nx - 1);
+  const bool xout = lane >= H && lane < 64 - H && x < nx;
+  const int nrows = a.rows + 2 * H;
+  const int ylo = y0 - H;
   const double gs0 = a.gs0;
   const double gs1 = a.gs1;
   // A tile is interior when every column and row it loads lies inside the
   // lattice: no masking there.
-  const bool interior = x0 - 2 * R >= 0 && x0 - 2 * R + 63 <= nx - 1 && ylo >= 0 && ylo + nrows - 1 <= ny - 1;
+  const bool interior = x0 - H >= 0 && x0 - H + 63 <= nx - 1 && ylo >= 0 && ylo + nrows - 1 <= ny - 1;
 
+  // Colour test.  (x + a y) mod C == colour  <=>  x mod C == (colour - a y)
+  // mod C; the right side is uniform across the wave and steps by -a mod C
+  // per row (kept in a scalar register), so each row costs one compare.
   const int C = __builtin_amdgcn_readfirstlane(a.colC);
   const int cx = xin ? x % C : -1 - 2 * C;
-  const int astep = __builtin_amdgcn_readfirstlane(a.cola % C);   // uniform: scalar arithmetic below
-  // (a y) mod C for y >= -5, uniform across the wave (kept in scalar registers)
-  auto row_part = [&](int y) -> int {
-    const int ym = ((y % C) + C) % C;
-    return __builtin_amdgcn_readfirstlane((astep * ym) % C);
-  };
-  auto advance = [&](int v) -> int {
-    v += astep;
-    return __builtin_amdgcn_readfirstlane(v >= C ? v - C : v);
-  };
-  // (cx + ay) mod C == colour  <=>  cx == (colour - ay) mod C, a uniform value
-  auto mine_at = [&](int ay) -> bool {
-    int t = colour - ay;
-    t += (t < 0) ? C : 0;
-    return cx == t;
-  };
+  const int astep = __builtin_amdgcn_readfirstlane(a.cola % C);
 
   // buffer resources over this probe's vectors and the observation planes
   const unsigned vbytes = (unsigned)(n * sizeof(T));
@@ -433,6 +418,9 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
   const __amdgpu_buffer_rsrc_t rs_pout = make_rsrc(a.p_out, vbytes);
   const __amdgpu_buffer_rsrc_t rs_obs = make_rsrc(OBS ? a.obs : a.r_in, OBS ? 9u * vbytes : vbytes);
   const unsigned lx = (unsigned)xc * (unsigned)sizeof(T);           // lane byte offset
+  // store offset: lanes outside the strip's output columns address past the
+  // end of the buffer, where the hardware range check drops the store
+  const unsigned lst = xout ? lx : 0xFFFFFFF0u;
   const unsigned rowb = (unsigned)nx * (unsigned)sizeof(T);         // row stride in bytes
 
 #pragma unroll
@@ -442,14 +430,30 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
   // FP64 in the plain form) as M v = kappa2 v + (4 v - neighbours): the
   // Laplacian's coefficients are exact in either type and only kappa2 is
   // rounded, so the rows of M and M @ M keep their exact sums.  The squared
-  // operator runs two such stages, s = M (M p).  Dot products are FP64.
+  // operator runs two such stages, s = M (M p).  Per-lane sums run in T over
+  // groups of five rows and are then added in FP64.
   const T k2_t = (T)a.kappa2, dk_t = (T)(a.kd - a.kappa2), tau_t = (T)a.tau, alpha_t = (T)alpha;
 
   auto march = [&](auto interior_tag) {
     constexpr bool IN = decltype(interior_tag)::value;
-    constexpr int NFULL = rows_full<R>() + 4 * R;
-    int ay_g = row_part(ylo - 1);
-    int ay_d = row_part(ylo - 2 * R);
+    constexpr int RF = rows_full<R>();
+    constexpr int NFULL = RF + 2 * H;
+    // (colour - a (y - 1)) mod C for the gradient row y - 1 of step 0
+    int tg;
+    {
+      const int yg = ylo - 1;
+      const int ay = (int)((((long)astep * (long)(((yg % C) + C) % C)) % C));
+      tg = colour - ay;
+      tg += tg < 0 ? C : 0;
+      tg = __builtin_amdgcn_readfirstlane(tg);
+    }
+    // byte offset of the arriving row y (interior tiles: ylo >= 0).  tg and yo
+    // pass through an empty asm statement once per step, so that the compiler
+    // derives each step's scalars in that step: in the straight-line interior
+    // code it would otherwise compute them all up front and run out of
+    // scalar registers.
+    unsigned yo = IN ? (unsigned)ylo * rowb : 0u;
+    const unsigned rowb5 = 5u * rowb, rowbR = (unsigned)R * rowb;
     T qr[5], qp[5];
     auto fetch = [&](int slot, int i) {
       const int yy = ylo + min(i, NFULL - 1);
@@ -460,16 +464,19 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
 #pragma unroll
     for (int u = 0; u < 5; ++u) fetch(u, u);
     // rings indexed by lattice row mod 5: t = M p and s = M t (or s = M p for
-    // the 5-point operator), tr = M r' and sr = M tr
-    T tacc[5], acc[5], tracc[5], acc2[5], obs_s[5], obs_r[5];
+    // the 5-point operator), tr = M r'
+    T tacc[5], acc[5], tracc[5], obs_s[5];
     // per-lane sums over the probe's sites (at most ceil(rows / C) terms):
-    // rho' and the gradient dots
-    T racc = T(0), gacc0 = T(0), gacc1 = T(0);
+    // rho' and the gradient dots; gamma' and delta' over the current group of
+    // five rows
+    T racc = T(0), gacc0 = T(0), gacc1 = T(0), g0 = T(0), g1 = T(0);
     T rq[5], pq[5], rnq[5], pl[5], pr[5], rl[5], rr[5];
+    bool mg[5];   // the lane's site of gradient row y - 1 is the probe's (ring by step)
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
-      tacc[u] = acc[u] = tracc[u] = acc2[u] = obs_s[u] = obs_r[u] = T(0);
+      tacc[u] = acc[u] = tracc[u] = obs_s[u] = T(0);
       rq[u] = pq[u] = rnq[u] = pl[u] = pr[u] = rl[u] = rr[u] = T(0);
+      mg[u] = false;
     }
     // one 5-point stage: value v of row y arrives in slot u of ring m; row
     // y - 1 of M v is complete afterwards and is returned
@@ -482,8 +489,7 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
       return done;
     };
     // A^T A planes of row y, loaded one step ahead at step y into slot u:
-    // used for p at step y + 1 (row y + 1 - 1) and for r' at step y + 3 (row
-    // ys - 1 = y)
+    // used for p at step y + 1 (row y) and for r' at step y + R + 1 (row yd = y)
     T opl[5][9];
 #pragma unroll
     for (int u = 0; u < 5; ++u)
@@ -513,16 +519,21 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
     // Interior tiles run the row loop fully unrolled (tiles have the standard
     // height): every prefetched value is then consumed in straight-line code
     // and the compiler keeps the loads in flight (a loop back edge would force
-    // it to wait for them).  Boundary tiles keep the loop: unrolled, their
-    // masking exhausts the registers.  (The row tests stay run-time branches:
-    // as compile-time constants they let the compiler stretch live ranges
-    // across the straight-line code, 85 -> 226 VGPRs.)
-#pragma unroll
-    for (int i0 = 0; i0 < (IN ? NFULL : nrows); i0 += 5) {
+    // it to wait for them), and every row test below is a compile-time
+    // constant.  Boundary tiles keep the loop and run-time row tests:
+    // unrolled, their masking exhausts the registers.
+    // five row steps starting at step i0 (ring slots are compile-time)
+    auto group = [&](int i0) {
 #pragma unroll
       for (int u = 0; u < 5; ++u) {
         const int i = i0 + u;
         const int y = ylo + i;
+        // rows of this step: gradient yg = y - 1, r' and stores ys = y - R,
+        // dot products yd = y - R - 1; each is one of the tile's own rows
+        // [y0, yb) for a contiguous range of steps
+        const bool g_row = IN ? (i >= H + 1 && i < H + 1 + RF) : (y - 1 >= y0 && y - 1 < yb);
+        const bool s_row = IN ? (i >= H + R && i < H + R + RF) : (y - R >= y0 && y - R < yb);
+        const bool d_row = IN ? (i >= H + R + 1 && i < H + R + 1 + RF) : (y - R - 1 >= y0 && y - R - 1 < yb);
         // ---- row y arrives: p_k = r_k + beta p_{k-1}
         T r_y = qr[u];
         T p_y = fma_t(beta_t, qp[u], qr[u]);
@@ -531,18 +542,35 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
           r_y = in ? r_y : T(0);
           p_y = in ? p_y : T(0);
         }
-        fetch(u, i + 5);
+        if constexpr (IN) {
+          __asm__ volatile("" : "+s"(yo), "+s"(tg));
+          // the last five steps prefetch nothing (no rows follow)
+          if (i + 5 < NFULL) {
+            qr[u] = buf_ld((T *)nullptr, rs_rin, lx, yo + rowb5);
+            qp[u] = buf_ld((T *)nullptr, rs_pin, lx, yo + rowb5);
+          }
+        } else {
+          fetch(u, i + 5);
+        }
         rq[u] = r_y;
         pq[u] = p_y;
         if constexpr (OBS) {
           pl[u] = from_left(p_y);
           pr[u] = from_right(p_y);
         }
+        // colour masks: row y - 1 now, row yd = y - R - 1 from R steps ago
+        const bool mine_g = cx == tg;
+        const bool mine_d = mg[(u + 5 - R) % 5];
+        mg[u] = mine_g;
+        tg -= astep;
+        tg += tg < 0 ? C : 0;
+        tg = __builtin_amdgcn_readfirstlane(tg);
         // t = M p: row y - 1 complete; for the squared operator it enters the
         // second stage, which completes row y - 2 of s = M t
         T tv = mstage(tacc, u, p_y);
         if constexpr (!IN) tv = (xin && y - 1 >= 0 && y - 1 < ny) ? tv : T(0);
-        if constexpr (R == 2) (void)mstage(acc, (u + 4) % 5, tv);
+        T sv = tv;                                                    // the fast path has scale 1
+        if constexpr (R == 2) sv = mstage(acc, (u + 4) % 5, tv);
         T ov = T(0);                                                  // (A^T A p) of row y - 1
         if constexpr (OBS) {
           load_planes(u, y);
@@ -552,52 +580,63 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
         if constexpr (NG > 0) {
           // (kd I + L) p = t + (kd - kappa2) p on row y - 1 over the probe's
           // sites (scaled at the end)
-          const int yg = y - 1;
-          if (yg >= y0 && yg < yb) {
-            const bool mine = mine_at(ay_g);
-            gacc0 += mine ? fma_t(dk_t, pq[(u + 4) % 5], tv) : T(0);
-            if constexpr (NG > 1 && OBS) gacc1 += mine ? ov : T(0);
+          if (g_row) {
+            gacc0 += mine_g ? fma_t(dk_t, pq[(u + 4) % 5], tv) : T(0);
+            if constexpr (NG > 1 && OBS) gacc1 += mine_g ? ov : T(0);
           }
         }
-        ay_g = advance(ay_g);
         // ---- row ys = y - R of s = Q p_k is complete: r_{k+1} = r_k - alpha s
         const int ys = y - R;
         const int us = (u + 5 - R) % 5;
-        T sv = R == 2 ? acc[us] : tv;                                 // the fast path has scale 1
         if constexpr (OBS) sv += obs_s[us];
         T rn = fma_t(-alpha_t, sv, rq[us]);
         if constexpr (!IN) rn = (xin && ys >= 0 && ys < ny) ? rn : T(0);
         rnq[us] = rn;
-        if (ys >= y0 && ys < yb) {
-          if (xout) {
-            buf_st(rn, rs_rout, lx, (unsigned)ys * rowb);
-            buf_st(pq[us], rs_pout, lx, (unsigned)ys * rowb);
-          }
+        if (s_row) {
+          const unsigned so = IN ? yo - rowbR : (unsigned)ys * rowb;
+          buf_st(rn, rs_rout, lst, so);
+          buf_st(pq[us], rs_pout, lst, so);
         }
-        // ---- row ys of r_{k+1} enters the Q r' stages
+        // ---- row ys of r_{k+1} enters the M r' stage: row yd = ys - 1 of
+        // M r' is complete
         if constexpr (OBS) {
           rl[us] = from_left(rn);
           rr[us] = from_right(rn);
         }
-        T trv = mstage(tracc, us, rn);
-        if constexpr (!IN) trv = (xin && ys - 1 >= 0 && ys - 1 < ny) ? trv : T(0);
-        if constexpr (R == 2) (void)mstage(acc2, (us + 4) % 5, trv);
-        else acc2[(us + 4) % 5] = trv;
-        if constexpr (OBS)
-          obs_r[(us + 4) % 5] = tau_t * obs_row((u + 2) % 5, ys - 1, rl, rnq, rr, (us + 3) % 5, (us + 4) % 5, us);
-        // ---- row yd = ys - R of Q r_{k+1} is complete: dot products (FP64)
-        const int yd = ys - R;
-        const int ud = (us + 5 - R) % 5;
-        if (yd >= y0 && yd < yb) {
-          T qv = acc2[ud];
-          if constexpr (OBS) qv += obs_r[ud];
-          const double r2 = (double)rnq[ud];
-          q[0] = __builtin_fma(r2, r2, q[0]);
-          q[1] = __builtin_fma(r2, (double)qv, q[1]);
-          racc += mine_at(ay_d) ? rnq[ud] : T(0);
+        const T trv = mstage(tracc, us, rn);
+        const int ud = (us + 4) % 5;
+        // ---- dot products on row yd: r'.Q r' = r'.M r' (R = 1) or
+        // |M r'|^2 (R = 2), plus r'.tau A^T A r'
+        if (d_row) {
+          const T rd = rnq[ud];
+          T qv = R == 2 ? trv * trv : rd * trv;
+          if constexpr (OBS)
+            qv = fma_t(rd, tau_t * obs_row((u + 4 - R) % 5, ys - 1, rl, rnq, rr, (us + 3) % 5, ud, us), qv);
+          g0 = fma_t(rd, rd, g0);
+          g1 += qv;
+          racc += mine_d ? rd : T(0);
         }
-        ay_d = advance(ay_d);
+        // keep the scheduler from interleaving row steps (it would stretch
+        // live ranges across the straight-line code)
+        if constexpr (IN) {
+          yo += rowb;
+          // the step's sums are complete here (the compiler would otherwise
+          // sink the masked additions to the end, holding every step's
+          // values and colour masks)
+          __asm__ volatile("" : "+v"(racc), "+v"(gacc0), "+v"(gacc1), "+v"(g0), "+v"(g1));
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
+      q[0] += (double)g0;
+      q[1] += (double)g1;
+      g0 = g1 = T(0);
+    };
+    if constexpr (IN) {
+#pragma unroll
+      for (int i0 = 0; i0 < NFULL; i0 += 5) group(i0);
+    } else {
+#pragma nounroll
+      for (int i0 = 0; i0 < nrows; i0 += 5) group(i0);
     }
     q[2] = (double)racc;
     if constexpr (NG > 0) q[LDQ_NQ_BASE] = gs0 * (double)gacc0;
@@ -710,7 +749,7 @@ static void launch_gen(const Pass2D<T> &a, bool squared, bool obs, int nblocks, 
     launch_ng<T, 1, false, GEN>(a, nblocks, stream);
 }
 
-// ngrad <= 2 (checked by the host driver for 2-D lattices); a.rows + 4R must
+// ngrad <= 2 (checked by the host driver for 2-D lattices); a.rows + 2H must
 // be a multiple of 5 (pass2d_rows).
 template <typename T>
 hipError_t launch_pass2d(const Pass2D<T> &a, bool squared, bool obs, bool fast, hipStream_t stream) {
@@ -741,17 +780,17 @@ hipError_t launch_pass2d(const Pass2D<T> &a, bool squared, bool obs, bool fast, 
 template hipError_t launch_pass2d<float>(const Pass2D<float> &, bool, bool, bool, hipStream_t);
 template hipError_t launch_pass2d<double>(const Pass2D<double> &, bool, bool, bool, hipStream_t);
 
-// Rows per wave tile near `want` with rows + 4R a multiple of 5.
+// Rows per wave tile near `want` with rows + 2H a multiple of 5 (halo H = R + 1).
 int pass2d_rows(bool squared, int want) {
-  const int R = squared ? 2 : 1;
+  const int H = squared ? 3 : 2;
   int rows = want < 1 ? 1 : want;
-  while ((rows + 4 * R) % 5 != 0) ++rows;
+  while ((rows + 2 * H) % 5 != 0) ++rows;
   return rows;
 }
 
-// Wave tiles: 64 - 4R columns by `rows` rows.
+// Wave tiles: 64 - 2H columns by `rows` rows.
 void pass2d_tiles(int nx, int ny, bool squared, int rows, int *tiles_x, int *ntiles) {
-  const int W = squared ? 56 : 60;
+  const int W = squared ? 58 : 60;
   *tiles_x = (nx + W - 1) / W;
   *ntiles = *tiles_x * ((ny + rows - 1) / rows);
 }
