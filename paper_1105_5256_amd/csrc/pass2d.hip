@@ -333,8 +333,8 @@ struct FastTile {
   T *r_out, *p_out;    // the probe's vectors
 };
 
-template <typename T, int R, bool OBS, int NG>
-__device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, double alpha, double beta, double *q);
+template <typename T, int R, bool OBS, int NG, typename Prologue>
+__device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prologue, double *q);
 
 template <typename T, int R, bool OBS, int NG>
 __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
@@ -342,8 +342,6 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int probe = L / a.ntiles, tile = L - probe * a.ntiles;
   const ProbeRef pref = probe_ref(a.tail, probe, a.ntiles);
-  const Step step = pass_prologue<1>(a.tail, pref, tile, a.ntiles, MODE_STEP);
-  if (!step.run) return;
   const size_t off = (size_t)probe * a.nx * a.ny;
   FastTile<T> ft;
   ft.nx = a.nx;
@@ -363,7 +361,8 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
   ft.r_out = a.r_out + off;
   ft.p_out = a.p_out + off;
   double q[NQ];
-  fast_tile<T, R, OBS, NG>(ft, tile, __builtin_amdgcn_readfirstlane(step.colour), step.alpha, step.beta, q);
+  auto prologue = [&]() { return pass_prologue<1>(a.tail, pref, tile, a.ntiles, MODE_STEP); };
+  if (!fast_tile<T, R, OBS, NG>(ft, tile, prologue, q)) return;
   pass_epilogue_n<NQ>(pref, tile, a.ntiles, q);
 }
 
@@ -377,14 +376,16 @@ constexpr int rows_full() {
 }
 
 // One tile of one probe: the march of the fused pass; q[] receives this
-// wave's sums of the pass's dot products.
-template <typename T, int R, bool OBS, int NG>
-__device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, double alpha, double beta, double *q) {
+// wave's sums of the pass's dot products.  The first rows of r and p are
+// requested before prologue() (the reduction of the previous launch's
+// partials, which yields alpha, beta and the probe's colour) so that its
+// memory round trips overlap; returns false when the probe is not active.
+template <typename T, int R, bool OBS, int NG, typename Prologue>
+__device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prologue, double *q) {
   constexpr int H = R + 1;
   constexpr int W = 64 - 2 * H;
   constexpr int NQ = LDQ_NQ_BASE + NG;
   const int lane = threadIdx.x & 63;
-  const T beta_t = (T)beta;
 
   const int nx = a.nx, ny = a.ny;
   const size_t n = (size_t)nx * ny;
@@ -422,6 +423,20 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
   // end of the buffer, where the hardware range check drops the store
   const unsigned lst = xout ? lx : 0xFFFFFFF0u;
   const unsigned rowb = (unsigned)nx * (unsigned)sizeof(T);         // row stride in bytes
+
+  // rows ylo .. ylo + 4 (clamped into the lattice), requested now
+  T qr0[5], qp0[5];
+#pragma unroll
+  for (int u = 0; u < 5; ++u) {
+    const unsigned so = (unsigned)min(max(ylo + u, 0), ny - 1) * rowb;
+    qr0[u] = buf_ld((T *)nullptr, rs_rin, lx, so);
+    qp0[u] = buf_ld((T *)nullptr, rs_pin, lx, so);
+  }
+  const Step step = prologue();
+  if (!step.run) return false;
+  const int colour = __builtin_amdgcn_readfirstlane(step.colour);
+  const double alpha = step.alpha, beta = step.beta;
+  const T beta_t = (T)beta;
 
 #pragma unroll
   for (int i = 0; i < NQ; ++i) q[i] = 0.0;
@@ -462,7 +477,10 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
       qp[slot] = buf_ld((T *)nullptr, rs_pin, lx, (unsigned)yc * rowb);
     };
 #pragma unroll
-    for (int u = 0; u < 5; ++u) fetch(u, u);
+    for (int u = 0; u < 5; ++u) {
+      qr[u] = qr0[u];
+      qp[u] = qp0[u];
+    }
     // rings indexed by lattice row mod 5: t = M p and s = M t (or s = M p for
     // the 5-point operator), tr = M r'
     T tacc[5], acc[5], tracc[5], obs_s[5];
@@ -650,6 +668,7 @@ __device__ inline void fast_tile(const FastTile<T> &a, int tile, int colour, dou
   // lanes outside the strip's output columns computed halo values only
 #pragma unroll
   for (int i = 0; i < NQ; ++i) q[i] = xout ? q[i] : 0.0;
+  return true;
 }
 
 // Batched STEP pass: one wave per work-list entry (field, probe, tile).
@@ -661,8 +680,6 @@ __global__ __launch_bounds__(64) void batch2d_fast(Batch2D<T> b) {
   const size_t po = (size_t)fd.part_off + (size_t)wk.probe * NQ * fd.ntiles;
   const ProbeRef pref{fd.item_base + wk.probe, b.tail.part_in + po, b.tail.part_out + po,
                       b.sigma + (size_t)wk.field * LDQ_MAXN};
-  const Step step = pass_prologue<1>(b.tail, pref, wk.tile, fd.ntiles, MODE_STEP);
-  if (!step.run) return;
   const size_t off = (size_t)fd.vec_off + (size_t)wk.probe * fd.nx * fd.ny;
   FastTile<T> ft;
   ft.nx = fd.nx;
@@ -682,7 +699,8 @@ __global__ __launch_bounds__(64) void batch2d_fast(Batch2D<T> b) {
   ft.r_out = b.r_out + off;
   ft.p_out = b.p_out + off;
   double q[NQ];
-  fast_tile<T, R, false, NG>(ft, wk.tile, __builtin_amdgcn_readfirstlane(step.colour), step.alpha, step.beta, q);
+  auto prologue = [&]() { return pass_prologue<1>(b.tail, pref, wk.tile, fd.ntiles, MODE_STEP); };
+  if (!fast_tile<T, R, false, NG>(ft, wk.tile, prologue, q)) return;
   pass_epilogue_n<NQ>(pref, wk.tile, fd.ntiles, q);
 }
 

@@ -116,6 +116,22 @@ __device__ inline bool shifts_update(const TailArgs &ta, const ProbeRef &pr, dou
 template <int NW>
 __device__ inline Step pass_prologue(const TailArgs &ta, const ProbeRef &pr, int tile, int ntiles, int mode) {
   double tot[LDQ_NQ_MAX];
+  const int nq = LDQ_NQ_BASE + ta.ngrad;
+  const bool owner = (tile == 0);
+  const int nred = owner ? nq : 2;
+  // the partials are read together with the state, before the state is
+  // inspected (one memory round trip instead of two; the partial buffers are
+  // allocated for every probe, and their values are used only when the probe
+  // is active and past its first pass)
+  double acc[LDQ_NQ_MAX];
+#pragma unroll
+  for (int i = 0; i < LDQ_NQ_MAX; ++i) acc[i] = 0.0;
+  const double *src = pr.pin;
+  for (int t = threadIdx.x; t < ntiles; t += NW * 64) {
+#pragma unroll
+    for (int i = 0; i < LDQ_NQ_MAX; ++i)
+      if (i < nred) acc[i] += src[(size_t)i * ntiles + t];
+  }
   const ProbeState in = ta.st_in[pr.st];
   Step step{false, in.colour, 0.0, 0.0};
   if (!in.active) {
@@ -125,18 +141,6 @@ __device__ inline Step pass_prologue(const TailArgs &ta, const ProbeRef &pr, int
   if (mode == MODE_INIT) {
     step.run = true;
     return step;
-  }
-  const int nq = LDQ_NQ_BASE + ta.ngrad;
-  const bool owner = (tile == 0);
-  const int nred = owner ? nq : 2;
-  double acc[LDQ_NQ_MAX];
-#pragma unroll
-  for (int i = 0; i < LDQ_NQ_MAX; ++i) acc[i] = 0.0;
-  const double *src = pr.pin;
-  for (int t = threadIdx.x; t < ntiles; t += NW * 64) {
-#pragma unroll
-    for (int i = 0; i < LDQ_NQ_MAX; ++i)
-      if (i < nred) acc[i] += src[(size_t)i * ntiles + t];
   }
   block_sum<NW>(acc, nred, tot);
 
