@@ -127,7 +127,9 @@ __device__ inline Step pass_prologue(const TailArgs &ta, const ProbeRef &pr, int
 #pragma unroll
   for (int i = 0; i < LDQ_NQ_MAX; ++i) acc[i] = 0.0;
   const double *src = pr.pin;
-  for (int t = threadIdx.x; t < ntiles; t += NW * 64) {
+  // NW = 1: one wave reduces on its own (it may be any wave of a larger workgroup)
+  const int tid = NW == 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+  for (int t = tid; t < ntiles; t += NW * 64) {
 #pragma unroll
     for (int i = 0; i < LDQ_NQ_MAX; ++i)
       if (i < nred) acc[i] += src[(size_t)i * ntiles + t];
@@ -263,13 +265,14 @@ __device__ inline void pass_epilogue(const TailArgs &ta, const ProbeRef &pr, int
   }
 }
 
-// Single-wave epilogue with a compile-time number of quantities.
+// Single-wave epilogue with a compile-time number of quantities (the wave
+// may be any wave of its workgroup).
 template <int NQ>
 __device__ inline void pass_epilogue_n(const ProbeRef &pr, int tile, int ntiles, const double *q) {
   double tot[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) tot[i] = wave_sum(q[i]);
-  if (threadIdx.x == 0) {
+  if ((threadIdx.x & 63) == 0) {
 #pragma unroll
     for (int i = 0; i < NQ; ++i) pr.pout[(size_t)i * ntiles + tile] = tot[i];
   }
