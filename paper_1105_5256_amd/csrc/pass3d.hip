@@ -409,12 +409,230 @@ __global__ __launch_bounds__(64 * T3W) void pass3d_fast(Pass3D<T> a) {
   pass_epilogue<T3W>(a.tail, pref, tile, a.ntiles, tot);
 }
 
+// Wide STEP pass for lattices at most 128 sites wide (an even number): lane
+// l owns the two consecutive columns 2l, 2l + 1 of a whole lattice row, so a
+// wave covers its row without an x-halo and with aligned 8-byte (FP64:
+// 16-byte) loads and stores; x-neighbours are the lane's other column or one
+// DPP shift away.  Otherwise as pass3d_fast (16 waves on the rows of a
+// T3Y-row tile and its y-halo, z marched with one LDS barrier per plane).
+// Its partial sums go to the slot of strip tile (0, ty, tz) of the strip
+// numbering shared with the other 3-D passes; the other strip slots of
+// (ty, tz) receive zeros.
+template <typename T, int NG, bool FIELD>
+__global__ __launch_bounds__(64 * T3W) void pass3d_wide(Pass3D<T> a) {
+  using P2 = Pair<T>;
+  constexpr int NQ = LDQ_NQ_BASE + NG;
+  constexpr int PF = 4;
+  __shared__ P2 sp[2][T3W][64];
+  __shared__ P2 srn[2][T3W][64];
+
+  const int tyz = a.tiles_y * a.nzseg;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int probe = L / tyz, rest = L - probe * tyz;
+  const int tyi = rest % a.tiles_y, tzi = rest / a.tiles_y;
+  const int tile = a.tiles_x * rest;            // strip tile (0, tyi, tzi)
+  const ProbeRef pref = probe_ref(a.tail, probe, a.ntiles);
+  const Step step = pass_prologue<T3W>(a.tail, pref, tile, a.ntiles, MODE_STEP);
+  if (!step.run) return;
+  const int colour = __builtin_amdgcn_readfirstlane(step.colour);
+  const T alpha_t = (T)step.alpha, beta_t = (T)step.beta;
+
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int y0 = tyi * T3Y, z0 = tzi * a.zseg;
+  const int z1 = min(z0 + a.zseg, nz);
+  const int xa = 2 * lane, y = y0 - 2 + w;
+  const bool xin = xa < nx, yin = y >= 0 && y < ny;
+  const bool in = xin && yin;
+  const bool own = xin && w >= 2 && w < T3W - 2 && y < ny;
+  const int yc = min(max(y, 0), ny - 1);
+
+  const size_t n = (size_t)nx * ny * nz;
+  const size_t off = (size_t)probe * n;
+  const unsigned vbytes = (unsigned)(n * sizeof(T));
+  const __amdgpu_buffer_rsrc_t rs_rin = make_rsrc(a.r_in + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_pin = make_rsrc(a.p_in + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_rout = make_rsrc(a.r_out + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_pout = make_rsrc(a.p_out + off, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_k2 = make_rsrc(FIELD ? a.kappa2_field : a.r_in, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_g0 = make_rsrc(NG > 0 ? a.grad[0].field : a.r_in, vbytes);
+  const __amdgpu_buffer_rsrc_t rs_g1 = make_rsrc(NG > 1 ? a.grad[1].field : a.r_in, vbytes);
+  // lane offset in a plane; lanes past the lattice's width address past the
+  // end of the buffers (loads read 0, stores are dropped)
+  const unsigned lo = xin ? ((unsigned)yc * (unsigned)nx + (unsigned)xa) * (unsigned)sizeof(T) : 0xFFFFFFF0u;
+  const unsigned planeb = (unsigned)nx * (unsigned)ny * (unsigned)sizeof(T);
+  const T k2c = (T)a.kappa2;
+  const T g0s = NG > 0 ? (T)a.grad[0].scale : T(0), g1s = NG > 1 ? (T)a.grad[1].scale : T(0);
+
+  const int C = __builtin_amdgcn_readfirstlane(a.colC);
+  const int cxa = xin ? xa % C : -1, cxb = xin ? (xa + 1) % C : -1;
+  const int ay = __builtin_amdgcn_readfirstlane((int)(((long)a.cola * ((y % C + C) % C)) % C));
+  const int bstep = __builtin_amdgcn_readfirstlane(a.colb % C);
+  auto bz_of = [&](int z) -> int {
+    return __builtin_amdgcn_readfirstlane((int)(((long)bstep * ((z % C + C) % C)) % C));
+  };
+  auto bz_next = [&](int bz) -> int {
+    bz += bstep;
+    return __builtin_amdgcn_readfirstlane(bz >= C ? bz - C : bz);
+  };
+  // x mod C that is the probe's colour on this row and the plane of bz
+  auto target = [&](int bz) -> int {
+    int t = colour - ay - bz;
+    t += (t < 0) ? C : 0;
+    t += (t < 0) ? C : 0;
+    return t;
+  };
+
+  P2 fr[PF + 1], fp[PF + 1], fk[PF + 1], fg0[PF + 1], fg1[PF + 1];
+  auto load_into = [&](int k, int z, int bz) {
+    const int zc = min(max(z, 0), nz - 1);
+    const unsigned so = (unsigned)zc * planeb;
+    fr[k] = buf_ld2((T *)nullptr, rs_rin, lo, so);
+    fp[k] = buf_ld2((T *)nullptr, rs_pin, lo, so);
+    if constexpr (FIELD) fk[k] = buf_ld2((T *)nullptr, rs_k2, lo, so);
+    if constexpr (NG > 0) {
+      // only pairs holding one of the probe's sites read memory (the other
+      // element is masked where the values are used)
+      const int tg = target(bz);
+      const bool use = own && z >= z0 && z < z1 && (cxa == tg || cxb == tg);
+      const unsigned go = use ? lo + so : 0xFFFFFFF0u;
+      fg0[k] = buf_ld2((T *)nullptr, rs_g0, go, 0u);
+      if constexpr (NG > 1) fg1[k] = buf_ld2((T *)nullptr, rs_g1, go, 0u);
+    }
+  };
+  auto form_p = [&](P2 r, P2 pv, int z) -> P2 {
+    const bool ok = in && z >= 0 && z < nz;
+    return P2{ok ? fma3(beta_t, pv.a, r.a) : T(0), ok ? fma3(beta_t, pv.b, r.b) : T(0)};
+  };
+  // 7-point stencil of Q on one plane: centre c, x-pair neighbours from the
+  // lane's own pair and the DPP shifts, y from LDS, z from the ring
+  auto apply = [&](P2 c, P2 up, P2 dn, P2 zm, P2 zp, P2 kk) -> P2 {
+    const T nba = (lane_left(c.b) + c.b) + (up.a + dn.a) + (zm.a + zp.a);
+    const T nbb = (c.a + lane_right(c.a)) + (up.b + dn.b) + (zm.b + zp.b);
+    return P2{fma3(kk.a, c.a, fma3(T(6), c.a, -nba)), fma3(kk.b, c.b, fma3(T(6), c.b, -nbb))};
+  };
+  const P2 zero{T(0), T(0)};
+  const P2 k2p{k2c, k2c};
+
+  double q0 = 0.0, q1 = 0.0;
+  T racc = T(0), g0acc = T(0), g1acc = T(0);
+
+  const int zs = z0 - 2;
+  int bz_l = bz_of(zs);
+#pragma unroll
+  for (int k = 0; k <= PF; ++k) {
+    load_into(k, zs + k, bz_l);
+    bz_l = bz_next(bz_l);
+  }
+  P2 pm = form_p(fr[0], fp[0], zs), pc = form_p(fr[1], fp[1], zs + 1);
+  const bool in1 = in && zs + 1 >= 0 && zs + 1 < nz;
+  P2 rc{in1 ? fr[1].a : T(0), in1 ? fr[1].b : T(0)};
+  P2 kc = FIELD ? fk[1] : k2p, km = zero;
+  P2 g0c = fg0[1], g1c = fg1[1];
+  load_into(0, zs + PF + 1, bz_l);
+  bz_l = bz_next(bz_l);
+  load_into(1, zs + PF + 2, bz_l);
+  bz_l = bz_next(bz_l);
+  P2 rnm2 = zero, rnm1 = zero;
+  int bz_m = bz_of(zs);
+
+  const int nsteps = z1 - zs;
+  for (int b = 0; b < nsteps; b += PF + 1) {
+#pragma unroll
+    for (int u = 0; u < PF + 1; ++u) {
+      const int i = b + u;
+      if (i >= nsteps) break;
+      const int t = zs + 1 + i;
+      const int sn = (u + 2) % (PF + 1);
+      const P2 rn1 = fr[sn], pn1raw = fp[sn];
+      const P2 pp = form_p(rn1, pn1raw, t + 1);
+      const bool inn = in && t + 1 >= 0 && t + 1 < nz;
+      const P2 kn = FIELD ? P2{inn ? fk[sn].a : T(0), inn ? fk[sn].b : T(0)} : k2p;
+      const P2 g0n = fg0[sn], g1n = fg1[sn];
+      load_into(sn, t + PF + 2, bz_l);
+      bz_l = bz_next(bz_l);
+      const bool tin = t >= 0 && t < nz;
+      sp[t & 1][w][lane] = pc;
+      lds_barrier();
+      const P2 up = (w > 0) ? sp[t & 1][w - 1][lane] : zero;
+      const P2 dn = (w < T3W - 1) ? sp[t & 1][w + 1][lane] : zero;
+      const P2 s = apply(pc, up, dn, pm, pp, FIELD ? kc : k2p);
+      const bool rin = in && tin;
+      const P2 rnew{rin ? fma3(-alpha_t, s.a, rc.a) : T(0), rin ? fma3(-alpha_t, s.b, rc.b) : T(0)};
+      const int bz_c = bz_next(bz_m);
+      if (own && t >= z0 && t < z1) {
+        const unsigned so = (unsigned)t * planeb;
+        buf_st2(rnew, rs_rout, lo, so);
+        buf_st2(pc, rs_pout, lo, so);
+        if constexpr (NG > 0) {
+          const int tg = target(bz_c);
+          const T ma = cxa == tg ? T(1) : T(0), mb = cxb == tg ? T(1) : T(0);
+          g0acc = fma3(ma * g0c.a, pc.a, fma3(mb * g0c.b, pc.b, g0acc));
+          if constexpr (NG > 1) g1acc = fma3(ma * g1c.a, pc.a, fma3(mb * g1c.b, pc.b, g1acc));
+        }
+      }
+      srn[t & 1][w][lane] = rnew;
+      if (t - 1 >= z0 && t - 1 < z1) {
+        const P2 upr = (w > 0) ? srn[(t - 1) & 1][w - 1][lane] : zero;
+        const P2 dnr = (w < T3W - 1) ? srn[(t - 1) & 1][w + 1][lane] : zero;
+        const P2 qr = apply(rnm1, upr, dnr, rnm2, rnew, FIELD ? km : k2p);
+        const double ra = (double)rnm1.a, rb = (double)rnm1.b;
+        q0 = __builtin_fma(ra, ra, q0);
+        q0 = __builtin_fma(rb, rb, q0);
+        q1 = __builtin_fma(ra, (double)qr.a, q1);
+        q1 = __builtin_fma(rb, (double)qr.b, q1);
+        const int tm = target(bz_m);
+        racc += (cxa == tm ? rnm1.a : T(0)) + (cxb == tm ? rnm1.b : T(0));
+      }
+      pm = pc;
+      pc = pp;
+      rc = P2{inn ? rn1.a : T(0), inn ? rn1.b : T(0)};
+      rnm2 = rnm1;
+      rnm1 = rnew;
+      km = kc;
+      kc = kn;
+      g0c = g0n;
+      g1c = g1n;
+      bz_m = bz_c;
+    }
+  }
+  double qv[NQ];
+  qv[0] = own ? q0 : 0.0;
+  qv[1] = own ? q1 : 0.0;
+  qv[2] = own ? (double)racc : 0.0;
+  if constexpr (NG > 0) qv[LDQ_NQ_BASE] = own ? (double)g0s * (double)g0acc : 0.0;
+  if constexpr (NG > 1) qv[LDQ_NQ_BASE + 1] = own ? (double)g1s * (double)g1acc : 0.0;
+  double tot[LDQ_NQ_MAX];
+#pragma unroll
+  for (int i = 0; i < LDQ_NQ_MAX; ++i) tot[i] = i < NQ ? qv[i] : 0.0;
+  pass_epilogue<T3W>(a.tail, pref, tile, a.ntiles, tot);
+  if (threadIdx.x == 0)
+    for (int tx = 1; tx < a.tiles_x; ++tx)
+      for (int i = 0; i < NQ; ++i) pref.pout[(size_t)i * a.ntiles + tile + tx] = 0.0;
+}
+
 // fast: STEP pass with a modular colouring, scale 1 and at most two diagonal
 // derivative operators (checked by the host driver)
 template <typename T>
 hipError_t launch_pass3d(const Pass3D<T> &a, bool fast, hipStream_t stream) {
   const int nblocks = a.ntiles * a.nprobes;
-  if (fast && a.mode == MODE_STEP) {
+  // the wide pass in FP32 only (its FP64 form needs more registers than a
+  // 16-wave workgroup leaves)
+  if (sizeof(T) == 4 && fast && a.mode == MODE_STEP && a.nx <= 128 && a.nx % 2 == 0) {
+    if constexpr (sizeof(T) == 4) {
+      const bool field = a.kappa2_field != nullptr;
+      const dim3 g(a.tiles_y * a.nzseg * a.nprobes), b(64 * T3W);
+      switch (a.tail.ngrad * 2 + (field ? 1 : 0)) {
+        case 0: hipLaunchKernelGGL((pass3d_wide<T, 0, false>), g, b, 0, stream, a); break;
+        case 1: hipLaunchKernelGGL((pass3d_wide<T, 0, true>), g, b, 0, stream, a); break;
+        case 2: hipLaunchKernelGGL((pass3d_wide<T, 1, false>), g, b, 0, stream, a); break;
+        case 3: hipLaunchKernelGGL((pass3d_wide<T, 1, true>), g, b, 0, stream, a); break;
+        case 4: hipLaunchKernelGGL((pass3d_wide<T, 2, false>), g, b, 0, stream, a); break;
+        default: hipLaunchKernelGGL((pass3d_wide<T, 2, true>), g, b, 0, stream, a); break;
+      }
+    }
+  } else if (fast && a.mode == MODE_STEP) {
     const bool field = a.kappa2_field != nullptr;
     const dim3 g(nblocks), b(64 * T3W);
     switch (a.tail.ngrad * 2 + (field ? 1 : 0)) {

@@ -200,6 +200,32 @@ def test_field3d_with_gradient(ctx, k, precision, tol, bound):
     assert rel(grad[0], G[0]) < bound and rel(grad[1], G[1]) < bound
 
 
+# 3-D lattices of the wide pass (two columns per lane, a whole row per wave:
+# widths up to 128, even) and of the strip pass (other widths), full lanes,
+# several y tiles and z segments, against the DST oracle and the FP64 form
+@pytest.mark.parametrize("shape", [(128, 24, 70), (127, 20, 33), (64, 30, 66)])
+def test_3d_wide_and_strip_passes(ctx, shape):
+    kappa2 = 0.3
+    say(f"3-D constant kappa2 {shape} mixed vs FP64 vs DST oracle")
+    n = int(np.prod(shape))
+    d = np.random.default_rng(17).uniform(0.5, 2.0, n)
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, kappa2))
+    D = ctx.op(ldq.ldq_op_diag(ctx.handle, d))
+    col = modular(shape, 2)
+    E, _ = estimator.estimator_dst(shape, kappa2, col, 1)
+    G, _ = gradient.grad_probing_dst(shape, kappa2, 1, col, [sp.diags(d)])
+    vm, gm, im = ldq.ldq_logdet_grad(ctx.handle, Q, [D], ldq.ldq_options_default(
+        k=2, nshifts=20, tol=1e-6, grad_tol=1e-7, precision=ldq.LDQ_MIXED))
+    vd, gd, idd = ldq.ldq_logdet_grad(ctx.handle, Q, [D], ldq.ldq_options_default(
+        k=2, nshifts=20, tol=1e-10, grad_tol=1e-10, precision=ldq.LDQ_FP64))
+    print(f"mixed {rel(vm, E):.2e} / {rel(gm[0], G[0]):.2e}, fp64 {rel(vd, E):.2e} / {rel(gd[0], G[0]):.2e}, "
+          f"mixed vs fp64 {rel(vm, vd):.2e} / {rel(gm[0], gd[0]):.2e}, iters {im['iters_max']} {idd['iters_max']}")
+    assert im["ncolours"] == 7 and im["enclosure_violations"] == 0
+    assert rel(vd, E) < 1e-9 and rel(gd[0], G[0]) < 1e-9
+    assert rel(vm, E) < 1e-5 and rel(gm[0], G[0]) < 1e-5
+    assert rel(vm, vd) < 1e-6 and rel(gm[0], gd[0]) < 1e-6
+
+
 # ------------------------------------------------- Gauss-linear posterior
 @pytest.mark.parametrize("precision,tol,bound", [(ldq.LDQ_FP64, 1e-10, 1e-9), (ldq.LDQ_MIXED, 1e-5, 1e-4)])
 def test_posterior_with_gradient(ctx, precision, tol, bound):
