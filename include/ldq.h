@@ -127,9 +127,13 @@ void ldq_op_destroy(ldq_op *op);
 
 /* --------------------------------------------------------------- options */
 
-enum { LDQ_FP64 = 0,    /* vectors stored in FP64 */
-       LDQ_MIXED = 1 }; /* vectors and operator fields stored in FP32; every product,
-                           update, dot and recurrence computed in FP64 */
+enum { LDQ_FP64 = 0,    /* vectors stored in FP64, all arithmetic in FP64 */
+       LDQ_MIXED = 1 }; /* vectors and operator fields stored in FP32.  The specialised
+                           lattice passes apply the stencil in FP32 with the Laplacian's exact
+                           coefficients (only kappa2 is rounded) and sum dot products per lane
+                           in FP32 over a few rows before adding them in FP64; the other passes
+                           compute in FP64.  CG scalars, shifts, recurrences, gradient and
+                           log-det accumulation are FP64 throughout. */
 enum {
   LDQ_COLOUR_AUTO = 0,     /* modular for lattice operators, greedy for CSR */
   LDQ_COLOUR_MODULAR = 1,  /* (x + a y [+ b z]) mod C, smallest valid C (lattices only) */
@@ -153,7 +157,18 @@ typedef struct {
   double lambda_min, lambda_max;/* spectrum enclosure; 0 => computed by the library */
   int probe_block;              /* probes advanced together (0 = all) */
   int check_every;              /* passes between convergence polls (0 = library default) */
+  int launch_mode;              /* LDQ_LAUNCH_*: how each chunk of pass launches between two polls
+                                   is issued */
+  int tile_rows;                /* 2-D lattices: lattice rows per wave tile; 0 = chosen by the
+                                   library's autotuner (timed once per problem shape on the context,
+                                   among the specialised pass's tile and shorter tiles of the general
+                                   pass) */
 } ldq_options;
+
+/* launch_mode: AUTO and GRAPH capture one chunk of Krylov pass launches into a HIP graph (on a
+ * stream the library owns; capture does not run anything) and replay it on the context stream for
+ * every chunk of a probe block; DIRECT enqueues the launches one by one.  Results are identical. */
+enum { LDQ_LAUNCH_AUTO = 0, LDQ_LAUNCH_GRAPH = 1, LDQ_LAUNCH_DIRECT = 2 };
 
 /* Defaults: k = 2, AUTO colouring, N = 20, tol = 1e-10 (FP64) / 1e-5 (MIXED),
  * grad_tol = 0, max_iter = 100000, FP64, enclosure computed, all probes. */

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -135,6 +136,8 @@ struct ldq_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evp[2] = {nullptr, nullptr};   // convergence polls
   int *hpin = nullptr;                      // pinned host copies of the device counters
+  hipStream_t cap = nullptr;                // stream for HIP graph capture (created on first use)
+  std::map<std::string, int> tuned_rows;    // autotuner choices for 2-D lattice problems
   std::vector<double> last_terms;
   int last_nparams = 0;
   int64_t last_count = 0;
@@ -237,6 +240,7 @@ extern "C" void ldq_destroy(ldq_ctx *c) {
   if (c->ev1) hipEventDestroy(c->ev1);
   for (hipEvent_t e : c->evp)
     if (e) hipEventDestroy(e);
+  if (c->cap) hipStreamDestroy(c->cap);
   if (c->hpin) hipHostFree(c->hpin);
   delete c;
 }
@@ -831,6 +835,8 @@ struct Call {
   bool estimated;                 // enclosure from the Lanczos estimate (refined when a probe contradicts it)
   int ntiles;
   int stats[8];
+  int rows2d;        // 2-D lattices: rows per wave tile (0: the specialised pass's standard tile)
+  double *tune_ms;   // non-null: a timing run of the autotuner (a few passes of the first probe block)
 };
 
 template <typename T>
@@ -921,6 +927,41 @@ static void lanczos_extremes(const double *h, int K, double *tmin, double *tmax)
   *tmax = bisect(K);
 }
 
+// A chunk of pass launches replayed from a HIP graph.  The launches are
+// captured once (on the library's own capture stream: capture executes
+// nothing, and the legacy default stream cannot be captured) and the graph
+// is launched on the context stream for every chunk.
+struct ChunkGraph {
+  hipGraphExec_t exec = nullptr;
+  ~ChunkGraph() {
+    if (exec) hipGraphExecDestroy(exec);
+  }
+};
+
+template <typename F>
+static int graph_chunk(ldq_ctx *c, ChunkGraph &g, F enqueue_on) {
+  if (!g.exec) {
+    if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_on(c->cap);
+    const hipError_t ec = hipStreamEndCapture(c->cap, &graph);
+    if (rc != LDQ_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    if (ec != hipSuccess) return fail(LDQ_E_DEVICE, "graph capture: %s", hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      g.exec = nullptr;
+      return fail(LDQ_E_DEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+    }
+  }
+  HIPCHK(hipGraphLaunch(g.exec, c->stream));
+  return LDQ_OK;
+}
+
 // Queue chunks of launches until the device counter `active` reads 0.  The
 // count after chunk c is copied to pinned host memory behind the chunk, and
 // the host waits for it only after queueing chunk c + 1, so the device does
@@ -1008,7 +1049,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   // tiles
   int tiles_x = 0, tiles_y = 0, nzseg = 0, ntiles = 0;
   const int zseg = 64;
-  const int rows2d = pass2d_rows(Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN, LDQ_ROWS2D);
+  const int rows2d = pass2d_rows(Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN, k.rows2d > 0 ? k.rows2d : LDQ_ROWS2D);
   if (is3d)
     pass3d_tiles((int)Q->shape[0], (int)Q->shape[1], (int)Q->shape[2], zseg, &tiles_x, &tiles_y, &nzseg, &ntiles);
   else
@@ -1116,7 +1157,9 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   // derivative operators, 32-bit byte offsets
   bool fast3d = is3d && !k.col.colours && Q->scale == 1.0 && P <= 2 && (double)Q->n * sizeof(T) < 4294967295.0;
   for (int i = 0; i < P; ++i) fast3d = fast3d && grads[i].kind == GK_DIAG;
-  // Launch with the probe state and partials read from buffer `in` and written to 1 - in.
+  // Launch with the probe state and partials read from buffer `in` and written to 1 - in,
+  // on stream ls (the context stream, or the capture stream while a chunk is captured).
+  hipStream_t ls = c->stream;
   auto launch = [&](int mode, int nprobes, int in, const T *rin, const T *pin, T *rout, T *pout) -> hipError_t {
     TailArgs t = ta;
     t.st_in = st[in];
@@ -1132,7 +1175,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
       a3.p_in = pin;
       a3.r_out = rout;
       a3.p_out = pout;
-      return launch_pass3d<T>(a3, fast3d, c->stream);
+      return launch_pass3d<T>(a3, fast3d, ls);
     }
     a2.mode = mode;
     a2.nprobes = nprobes;
@@ -1140,8 +1183,9 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     a2.p_in = pin;
     a2.r_out = rout;
     a2.p_out = pout;
-    return launch_pass2d<T>(a2, sq, has_obs, fast2d, c->stream);
+    return launch_pass2d<T>(a2, sq, has_obs, fast2d, ls);
   };
+  const bool graphs = k.o.launch_mode != LDQ_LAUNCH_DIRECT;
 
   // an even number of passes per chunk keeps every chunk on the same buffer parity
   const int check = k.o.check_every > 0 ? 2 * ((k.o.check_every + 1) / 2) : 16;
@@ -1161,17 +1205,39 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     HIPCHK(launch(MODE_INIT, nb, 0, nullptr, nullptr, nullptr, nullptr));
     HIPCHK(launch(MODE_FIRST, nb, 0, nullptr, nullptr, bufA_r, bufA_p));
     passes += 2;
+    if (k.tune_ms) {
+      // autotuner timing run: a few STEP passes of this block, then stop
+      constexpr int TUNE_STEPS = 6;
+      HIPCHK(hipEventRecord(c->ev0, c->stream));
+      for (int i = 0; i < TUNE_STEPS; ++i)
+        HIPCHK(i % 2 == 0 ? launch(MODE_STEP, nb, 1, bufA_r, bufA_p, bufB_r, bufB_p)
+                          : launch(MODE_STEP, nb, 0, bufB_r, bufB_p, bufA_r, bufA_p));
+      HIPCHK(hipEventRecord(c->ev1, c->stream));
+      HIPCHK(hipEventSynchronize(c->ev1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      *k.tune_ms = ms;
+      return LDQ_OK;
+    }
+    // a chunk is an even number of passes, so every chunk starts from the
+    // same buffers and one captured graph serves all chunks of the block
     bool in_a = true;
-    auto chunk = [&]() -> int {
+    auto steps = [&](hipStream_t s) -> int {
+      ls = s;
       for (int i = 0; i < check; ++i) {
-        if (in_a)
-          HIPCHK(launch(MODE_STEP, nb, 1, bufA_r, bufA_p, bufB_r, bufB_p));
-        else
-          HIPCHK(launch(MODE_STEP, nb, 0, bufB_r, bufB_p, bufA_r, bufA_p));
+        const hipError_t e = in_a ? launch(MODE_STEP, nb, 1, bufA_r, bufA_p, bufB_r, bufB_p)
+                                  : launch(MODE_STEP, nb, 0, bufB_r, bufB_p, bufA_r, bufA_p);
         in_a = !in_a;
+        if (e != hipSuccess) {
+          ls = c->stream;
+          return fail(LDQ_E_DEVICE, "pass launch: %s", hipGetErrorString(e));
+        }
       }
+      ls = c->stream;
       return LDQ_OK;
     };
+    ChunkGraph cg;
+    auto chunk = [&]() -> int { return graphs ? graph_chunk(c, cg, steps) : steps(c->stream); };
     int64_t chunks = 0;
     bool st_block = false;
     CHK(poll_chunks(c, active_count, chunk, ((int64_t)k.o.max_iter + 2 * check) / check + 1, &chunks, &st_block));
@@ -1650,6 +1716,53 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
   return LDQ_OK;
 }
 
+// Autotuner for 2-D lattices: the tile height decides the work per wave
+// (rows + halo row steps) against the number of waves and, at the standard
+// height, selects the specialised pass.  Large lattices have waves to spare
+// and want long tiles; small ones are latency-bound and want many short
+// tiles.  Each candidate is timed over a few STEP passes of the first probe
+// block; the choice is kept on the context for the problem's signature.
+static int tune_rows(Call &k) {
+  ldq_op *Q = k.Q;
+  k.rows2d = 0;
+  if (Q->ndim != 2) return LDQ_OK;
+  const bool sq = Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN;
+  if (k.o.tile_rows > 0) {
+    k.rows2d = pass2d_rows(sq, k.o.tile_rows);
+    return LDQ_OK;
+  }
+  char key[256];
+  std::snprintf(key, sizeof key, "%lld,%lld,%d,%d,%d,%d,%d,%d,%d,%d", (long long)Q->shape[0], (long long)Q->shape[1],
+                Q->lkind, k.o.precision, k.nparams, Q->obs9 != nullptr, k.col.colours != nullptr,
+                Q->field != nullptr, (int)k.classes.size(), k.o.probe_block);
+  auto it = k.c->tuned_rows.find(key);
+  if (it != k.c->tuned_rows.end()) {
+    k.rows2d = it->second;
+    return LDQ_OK;
+  }
+  const int cands[4] = {LDQ_ROWS2D, 4, 9, 16};
+  int best = 0;
+  double best_ms = 0.0;
+  for (int want : cands) {
+    const int rows = pass2d_rows(sq, want);
+    if (want != LDQ_ROWS2D && rows >= pass2d_rows(sq, LDQ_ROWS2D)) continue;
+    double ms = 0.0;
+    k.rows2d = rows;
+    k.tune_ms = &ms;
+    const int st = (k.o.precision == LDQ_MIXED) ? run_krylov<float>(k, nullptr, nullptr)
+                                                : run_krylov<double>(k, nullptr, nullptr);
+    k.tune_ms = nullptr;
+    if (st != LDQ_OK) return st;
+    if (best == 0 || ms < best_ms) {
+      best = rows;
+      best_ms = ms;
+    }
+  }
+  k.rows2d = best;
+  k.c->tuned_rows[key] = best;
+  return LDQ_OK;
+}
+
 static int logdet_impl(ldq_ctx *c, const ldq_op *Q, int nparams, const ldq_op *const *dQ, const ldq_options *opts,
                        double *logdet, double *grad, ldq_info *info) {
   auto t0 = std::chrono::steady_clock::now();
@@ -1658,10 +1771,12 @@ static int logdet_impl(ldq_ctx *c, const ldq_op *Q, int nparams, const ldq_op *c
   double sums[1 + LDQ_MAXP] = {};
   ldq_info tmp{};
   int st;
-  if (k.Q->kind == OPK_CSR)
+  if (k.Q->kind == OPK_CSR) {
     st = (k.o.precision == LDQ_MIXED) ? run_krylov_csr<float>(k, &tmp, sums) : run_krylov_csr<double>(k, &tmp, sums);
-  else
+  } else {
+    CHK(tune_rows(k));
     st = (k.o.precision == LDQ_MIXED) ? run_krylov<float>(k, &tmp, sums) : run_krylov<double>(k, &tmp, sums);
+  }
   if (st != LDQ_OK && st != LDQ_E_NO_CONVERGENCE) return st;
   if (logdet) *logdet = sums[0];
   if (grad)

@@ -22,6 +22,7 @@ LDQ_SHIFTED_LAPLACIAN, LDQ_SQUARED_SHIFTED_LAPLACIAN = 1, 2
 LDQ_FLAG_DEVICE_PTR = 1
 LDQ_FP64, LDQ_MIXED = 0, 1
 LDQ_COLOUR_AUTO, LDQ_COLOUR_MODULAR, LDQ_COLOUR_GREEDY, LDQ_COLOUR_USER, LDQ_COLOUR_IDENTITY = 0, 1, 2, 3, 4
+LDQ_LAUNCH_AUTO, LDQ_LAUNCH_GRAPH, LDQ_LAUNCH_DIRECT = 0, 1, 2
 
 
 class ldq_options(ctypes.Structure):
@@ -39,6 +40,8 @@ class ldq_options(ctypes.Structure):
         ("lambda_max", ctypes.c_double),
         ("probe_block", ctypes.c_int),
         ("check_every", ctypes.c_int),
+        ("launch_mode", ctypes.c_int),
+        ("tile_rows", ctypes.c_int),
     ]
 
 

@@ -53,7 +53,8 @@ def test_batched_equals_single_calls_and_oracle(ctx, precision, tol, gtol, bound
     fields = wl["fields"] + [dict(kind="sq", shape=(90, 23), kappa2=0.02, power=2, k=4)]
     say(f"batched {len(fields)} fields, sides {[f['shape'] for f in fields]}, precision={precision}")
     Qs, dQs = make_fields(ctx, fields)
-    opts = ldq.ldq_options_default(k=4, nshifts=20, tol=tol, grad_tol=gtol, precision=precision)
+    # single calls on the batched pass's tile height (not the autotuner's choice)
+    opts = ldq.ldq_options_default(k=4, nshifts=20, tol=tol, grad_tol=gtol, precision=precision, tile_rows=32)
     vals, grads, infos = ldq.ldq_logdet_batched(ctx.handle, Qs, dQs, opts)
     terms = ldq.ldq_probe_terms(ctx.handle)
     C, co = colouring.find_modular(2, 8)

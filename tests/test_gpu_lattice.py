@@ -226,6 +226,47 @@ def test_3d_wide_and_strip_passes(ctx, shape):
     assert rel(vm, vd) < 1e-6 and rel(gm[0], gd[0]) < 1e-6
 
 
+# graph-replayed chunks of pass launches against launches enqueued one by
+# one: the same kernels with the same arguments, so results are identical
+@pytest.mark.parametrize("shape,kind,k,precision", [((96, 70), ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, 4, ldq.LDQ_MIXED),
+                                                    ((64, 64), ldq.LDQ_SHIFTED_LAPLACIAN, 2, ldq.LDQ_FP64),
+                                                    ((40, 22, 30), ldq.LDQ_SHIFTED_LAPLACIAN, 2, ldq.LDQ_MIXED)])
+def test_graph_and_direct_launches_agree(ctx, shape, kind, k, precision):
+    say(f"graph vs direct launches {shape} kind={kind} precision={precision}")
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, kind, 0.07))
+    dQ = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, 0.07, scale=2.0)) \
+        if kind == ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN else ctx.op(ldq.ldq_op_diag(ctx.handle, np.ones(int(np.prod(shape)))))
+    res = []
+    for mode in (ldq.LDQ_LAUNCH_DIRECT, ldq.LDQ_LAUNCH_GRAPH, ldq.LDQ_LAUNCH_AUTO):
+        # probe blocks of 3 and polls every 6 passes: several blocks, several chunks each
+        opts = ldq.ldq_options_default(k=k, tol=1e-6, grad_tol=1e-7, precision=precision, probe_block=3,
+                                       check_every=6, launch_mode=mode)
+        v, g, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
+        res.append((v, g[0], info["iters_total"], ldq.ldq_probe_terms(ctx.handle)))
+    for r in res[1:]:
+        assert r[0] == res[0][0] and r[1] == res[0][1] and r[2] == res[0][2]
+        assert np.array_equal(r[3], res[0][3])
+
+
+# tile heights (the autotuner's candidates and its choice) change only the
+# order of the dot-product sums
+@pytest.mark.parametrize("shape,kind,k", [((64, 64), ldq.LDQ_SHIFTED_LAPLACIAN, 2),
+                                          ((90, 77), ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, 4)])
+def test_tile_rows_and_autotuner(ctx, shape, kind, k):
+    say(f"tile heights {shape} kind={kind}")
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, kind, 0.1))
+    n = int(np.prod(shape))
+    D = ctx.op(ldq.ldq_op_diag(ctx.handle, np.linspace(0.5, 1.5, n)))
+    res = {}
+    for rows in (0, 4, 9, 16, 32):
+        opts = ldq.ldq_options_default(k=k, tol=1e-11, grad_tol=1e-11, tile_rows=rows)
+        v, g, _ = ldq.ldq_logdet_grad(ctx.handle, Q, [D], opts)
+        res[rows] = (v, g[0])
+    ref = res[32]
+    for rows, (v, g) in res.items():
+        assert rel(v, ref[0]) < 1e-12 and rel(g, ref[1]) < 1e-11, rows
+
+
 # ------------------------------------------------- Gauss-linear posterior
 @pytest.mark.parametrize("precision,tol,bound", [(ldq.LDQ_FP64, 1e-10, 1e-9), (ldq.LDQ_MIXED, 1e-5, 1e-4)])
 def test_posterior_with_gradient(ctx, precision, tol, bound):
