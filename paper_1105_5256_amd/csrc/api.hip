@@ -8,7 +8,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -649,7 +651,21 @@ static bool modular_ok(int dim, int D, int C, int a, int b) {
   return true;
 }
 
+// The search result depends only on (dim, D); it is kept for the process
+// (the 3-D search at radius 6 visits ~10^7 candidates).
 static int modular_params(int dim, int D, int *C, int *a, int *b) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, std::array<int, 3>> found;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = found.find({dim, D});
+    if (it != found.end()) {
+      *C = it->second[0];
+      *a = it->second[1];
+      *b = it->second[2];
+      return LDQ_OK;
+    }
+  }
   for (int c = 1; c <= 4096; ++c) {
     for (int x = 0; x < c; ++x)
       for (int y = 0; y < (dim == 3 ? c : 1); ++y)
@@ -657,6 +673,8 @@ static int modular_params(int dim, int D, int *C, int *a, int *b) {
           *C = c;
           *a = x;
           *b = y;
+          std::lock_guard<std::mutex> lock(mu);
+          found[{dim, D}] = {c, x, y};
           return LDQ_OK;
         }
   }
