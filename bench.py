@@ -4,10 +4,18 @@
 Default workload (the configuration the headline metric is quoted on): the
 2-D 512 x 512 lattice with Q = (0.05 I + L)^2 (13-point operator), distance-4
 modular colouring (41 probes), N = 20 contour shifts, gradient with respect
-to kappa^2 (dQ/dkappa^2 = 2 (kappa^2 I + L)), mixed form (vectors stored in
-FP32, all arithmetic in FP64), tol 1e-5 per shifted system and 1e-6 for the
-base system.  One step = one full log det + gradient evaluation through the
-C ABI with the operator already resident on the device.
+to kappa^2 (dQ/dkappa^2 = 2 (kappa^2 I + L)), mixed form (vectors and stencil
+arithmetic in FP32, CG scalars, shifts and accumulation in FP64), tol 1e-4
+per shifted system and 1e-4 for the base system.  One step = one full log
+det + gradient evaluation through the C ABI with the operator already
+resident on the device.
+
+Tolerances: the metric is throughput at a relative error of at most 1e-4
+against FP64, so the mixed workloads run at the loosest tolerance of the
+range 1e-4 .. 1e-6 given for the mixed form of this workload (tol = grad_tol
+= 1e-4); every run prints the error of its result against a tight (1e-10)
+FP64 run of the same library (rel_err_vs_fp64), which is what the 1e-4 gate
+is checked on.  The paper itself iterates to a relative tolerance of 1e-3.
 
 --config selects one of the other workloads (each printed the same way):
   lattice64_5pt   64 x 64, Q = 0.1 I + L, distance 2 (5 probes), FP64, tol 1e-10
@@ -81,7 +89,7 @@ class Workload:
             self.wl = wl
             self.Q = ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SQUARED_SHIFTED_LAPLACIAN, wl["kappa2"]))
             self.dQ = [ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SHIFTED_LAPLACIAN, wl["kappa2"], scale=2.0))]
-            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 4, 1e-5, 1e-6
+            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 4, 1e-4, 1e-4
             self.describe = ("lattice512_sq: 2-D 512x512 lattice, Q = (0.05 I + L)^2 (13-point), distance-4 "
                              "modular colouring (41 probes), N=20 shifts, log det + d/dkappa2")
             self.kernel = "pass2d_fast<float, R=2, no observations, 1 gradient> (fused 2-D pass)"
@@ -102,7 +110,7 @@ class Workload:
             self.Q = ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SHIFTED_LAPLACIAN, 0.0,
                                              kappa2_field=wl["kappa2_field"]))
             self.dQ = [ctx.op(L.ldq_op_diag(h, d)) for d in wl["dkappa2"]]
-            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 6, 1e-5, 1e-6
+            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 6, 1e-4, 1e-4
             self.describe = ("field128: 3-D 128^3 lattice, Q = diag(kappa2(s)) + L (7-point), log kappa2 = "
                              "log 0.1 + 0.5 z(s), distance-6 modular colouring (70 probes), N=20 shifts, "
                              "log det + d/d(eta0, eta1)")
@@ -116,7 +124,7 @@ class Workload:
             dk = ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SHIFTED_LAPLACIAN, wl["kappa2"], scale=2.0))
             dt = ctx.op(L.ldq_op_obs_gram(h, self.Q, wl["corner"], wl["weight"]))
             self.dQ = [dk, dt]
-            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 4, 1e-5, 1e-6
+            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 4, 1e-4, 1e-4
             self.describe = ("posterior1024: 2-D 1024x1024 lattice, Q = (0.05 I + L)^2 + 100 A^T A, 100000 "
                              "bilinear observations, distance-4 modular colouring (41 probes), N=20 shifts, "
                              "log det + d/d(kappa2, tau)")
@@ -132,7 +140,7 @@ class Workload:
                                                        f["kappa2"])))
                 self.dQs.append([ctx.op(L.ldq_op_lattice(h, f["shape"], L.LDQ_SHIFTED_LAPLACIAN, f["kappa2"],
                                                          scale=2.0))])
-            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 4, 1e-5, 1e-6
+            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 4, 1e-4, 1e-4
             self.describe = ("batch256: 256 independent 2-D fields (kappa2_f I + L)^2, sides U{32..256}, "
                              "kappa2_f LogUniform(0.01, 1), distance-4 modular colouring (41 probes each), "
                              "N=20 shifts, log det + d/dkappa2 per field, one batched call")
@@ -245,10 +253,10 @@ def _n_of(w, j):
 
 
 # ----------------------------------------------------------------- the CSR form
-def csr_forms(ctx, wl, nsteps, ref_val, ref_grad):
+def csr_forms(ctx, wl, nsteps, ref_val, ref_grad, tol, gtol):
     """The 512x512 workload with Q and dQ/dkappa2 given as CSR matrices (the
-    general sparse passes), the same colouring and enclosure as the stencil
-    form, timed in the mixed and FP64 forms."""
+    general sparse passes), the same colouring, enclosure and tolerances as the
+    stencil form, timed in the mixed and FP64 forms."""
     import torch
 
     from paper_1105_5256_amd import ldq, workloads
@@ -264,7 +272,7 @@ def csr_forms(ctx, wl, nsteps, ref_val, ref_grad):
     dQ = ctx.op(ldq.ldq_op_csr(ctx.handle, n, rp, ci, v))
     res = {}
     for name, prec in [("csr_mixed", ldq.LDQ_MIXED), ("csr_fp64", ldq.LDQ_FP64)]:
-        opts = ldq.ldq_options_default(k=wl["k"], nshifts=20, tol=1e-5, grad_tol=1e-6, precision=prec,
+        opts = ldq.ldq_options_default(k=wl["k"], nshifts=20, tol=tol, grad_tol=gtol, precision=prec,
                                        colouring=ldq.LDQ_COLOUR_USER, user_colours=col, lambda_min=lo,
                                        lambda_max=hi)
         ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
@@ -345,7 +353,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.describe, "n": w.n, "probes": sum(i["ncolours"] for i in one_eval),
                    "nshifts": 20, "tol": w.tol, "grad_tol": w.gtol,
-                   "storage": "f32 vectors, f64 arithmetic" if w.timed == ldq.LDQ_MIXED else "f64",
+                   "storage": "f32 vectors and stencil arithmetic, f64 scalars" if w.timed == ldq.LDQ_MIXED else "f64",
                    "iters_max": max(i["iters_max"] for i in one_eval), "parallelism": "one GPU"},
         "roofline": roofline,
     }
@@ -374,7 +382,7 @@ def main():
         }
         progress(f"{oname} form done")
         if args.config == "lattice512_sq":
-            out["forms"].update(csr_forms(ctx, w.wl, max(2, steps // 3), rv[0], rg[0][0]))
+            out["forms"].update(csr_forms(ctx, w.wl, max(2, steps // 3), rv[0], rg[0][0], w.tol, w.gtol))
             progress("CSR forms done")
 
     if args.copy_calibration:
