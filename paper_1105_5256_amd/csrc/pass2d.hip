@@ -506,34 +506,42 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
       m[(u + 1) % 5] = -v;
       return done;
     };
-    // A^T A planes of row y, loaded one step ahead at step y into slot u:
-    // used for p at step y + 1 (row y) and for r' at step y + R + 1 (row yd = y)
-    T opl[5][9];
+    // A^T A is symmetric: its coefficient from site s to s + d equals the one
+    // from s + d to s, so planes 5..8 of a row are planes 3..0 of the next
+    // site or row (equal bit for bit: both entries accumulate the same
+    // products in the same order).  Only planes 0..4 are loaded, those of row
+    // y + 1 at step y into slot (u + 1) mod 5: at step y the planes of rows
+    // y - 1 and y serve p's row y - 1, those of rows yd and yd + 1 r' row yd.
+    T opl[5][5];
 #pragma unroll
     for (int u = 0; u < 5; ++u)
 #pragma unroll
-      for (int d = 0; d < 9; ++d) opl[u][d] = T(0);
+      for (int d = 0; d < 5; ++d) opl[u][d] = T(0);
     auto load_planes = [&](int slot, int yo) {
-      const int yoc = IN ? yo : min(max(yo, 0), ny - 1);
+      const int yoc = min(max(yo, 0), ny - 1);
       const unsigned so = (unsigned)yoc * rowb;
 #pragma unroll
-      for (int d = 0; d < 9; ++d) opl[slot][d] = buf_ld((T *)nullptr, rs_obs, lx, so + (unsigned)d * vbytes);
+      for (int d = 0; d < 5; ++d) opl[slot][d] = buf_ld((T *)nullptr, rs_obs, lx, so + (unsigned)d * vbytes);
     };
-    // (A^T A v) of row yo from the planes in `slot` and the v rows held in the
-    // (l, c, r) rings at slots um, uc, up
-    auto obs_row = [&](int slot, int yo, const T *lm, const T *cm, const T *rm, int um, int uc, int up) -> T {
-      const T *o = opl[slot];
+    // (A^T A v) of row yo from the planes of rows yo (slot sc) and yo + 1
+    // (slot sn) and the v rows held in the (l, c, r) rings at slots um, uc, up
+    // (lanes 0 and 63 read 0 for the shifted terms: halo columns whose sums
+    // are not used)
+    auto obs_row = [&](int sc, int sn, int yo, const T *lm, const T *cm, const T *rm, int um, int uc, int up) -> T {
+      const T *o = opl[sc];
+      const T *on = opl[sn];
       T v = o[0] * lm[um];
       v = fma_t(o[1], cm[um], v);
       v = fma_t(o[2], rm[um], v);
       v = fma_t(o[3], lm[uc], v);
       v = fma_t(o[4], cm[uc], v);
-      v = fma_t(o[5], rm[uc], v);
-      v = fma_t(o[6], lm[up], v);
-      v = fma_t(o[7], cm[up], v);
-      v = fma_t(o[8], rm[up], v);
+      v = fma_t(from_right(o[3]), rm[uc], v);     // plane 5 = plane 3 at x + 1
+      v = fma_t(from_left(on[2]), lm[up], v);     // plane 6 = plane 2 at (x - 1, y + 1)
+      v = fma_t(on[1], cm[up], v);                // plane 7 = plane 1 at (x, y + 1)
+      v = fma_t(from_right(on[0]), rm[up], v);    // plane 8 = plane 0 at (x + 1, y + 1)
       return (IN || (yo >= 0 && yo < ny)) ? v : T(0);
     };
+    if constexpr (OBS) load_planes(0, ylo);
     // Interior tiles run the row loop fully unrolled (tiles have the standard
     // height): every prefetched value is then consumed in straight-line code
     // and the compiler keeps the loads in flight (a loop back edge would force
@@ -591,8 +599,8 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
         if constexpr (R == 2) sv = mstage(acc, (u + 4) % 5, tv);
         T ov = T(0);                                                  // (A^T A p) of row y - 1
         if constexpr (OBS) {
-          load_planes(u, y);
-          ov = obs_row((u + 4) % 5, y - 1, pl, pq, pr, (u + 3) % 5, (u + 4) % 5, u);
+          load_planes((u + 1) % 5, y + 1);
+          ov = obs_row((u + 4) % 5, u, y - 1, pl, pq, pr, (u + 3) % 5, (u + 4) % 5, u);
           obs_s[(u + 4) % 5] = tau_t * ov;
         }
         if constexpr (NG > 0) {
@@ -629,7 +637,8 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
           const T rd = rnq[ud];
           T qv = R == 2 ? trv * trv : rd * trv;
           if constexpr (OBS)
-            qv = fma_t(rd, tau_t * obs_row((u + 4 - R) % 5, ys - 1, rl, rnq, rr, (us + 3) % 5, ud, us), qv);
+            qv = fma_t(rd, tau_t * obs_row((u + 4 - R) % 5, (u + 5 - R) % 5, ys - 1, rl, rnq, rr, (us + 3) % 5, ud, us),
+                       qv);
           g0 = fma_t(rd, rd, g0);
           g1 += qv;
           racc += mine_d ? rd : T(0);
