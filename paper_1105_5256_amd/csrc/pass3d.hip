@@ -218,8 +218,14 @@ template <typename T, int NG, bool FIELD>
 __global__ __launch_bounds__(64 * T3W) void pass3d_fast(Pass3D<T> a) {
   constexpr int NQ = LDQ_NQ_BASE + NG;
   constexpr int PF = 4;                       // prefetch distance in planes
-  __shared__ T sp[2][T3W][64];
-  __shared__ T srn[2][T3W][64];
+  // row buffers of p and r' per step parity; rows 0 and T3W + 1 stay 0 (the
+  // missing neighbours of the outer waves), so every read is unconditional
+  __shared__ T sp[2][T3W + 2][64];
+  __shared__ T srn[2][T3W + 2][64];
+  for (int k = threadIdx.x; k < 2 * (T3W + 2) * 64; k += blockDim.x) {
+    (&sp[0][0][0])[k] = T(0);
+    (&srn[0][0][0])[k] = T(0);
+  }
 
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int probe = L / a.ntiles, tile = L - probe * a.ntiles;
@@ -332,12 +338,16 @@ __global__ __launch_bounds__(64 * T3W) void pass3d_fast(Pass3D<T> a) {
 
   // the ring slot of plane z is (z - zs) mod (PF + 1); the loop is unrolled by
   // PF + 1 so slots are compile-time
-  const int nsteps = z1 - zs;    // steps t = zs + 1 .. z1
-  for (int b = 0; b < nsteps; b += PF + 1) {
+  // steps t = zs + 1 .. z1, padded to whole pairs of rings: the extra steps store
+  // nothing and add no dot products (their planes fail the z0 <= t < z1
+  // tests), and with no exit inside the unrolled ring the compiler does not
+  // wait for every load in flight at the exit's join
+  constexpr int RING2 = 2 * (PF + 1);   // two rings per loop iteration
+  const int nsteps = (z1 - zs + RING2 - 1) / RING2 * RING2;
+  for (int b = 0; b < nsteps; b += RING2) {
 #pragma unroll
-    for (int u = 0; u < PF + 1; ++u) {
+    for (int u = 0; u < RING2; ++u) {
       const int i = b + u;
-      if (i >= nsteps) break;
       const int t = zs + 1 + i;
       // plane t + 1 of p from the ring, then refill its slot with plane t + 1 + PF
       const int sn = (u + 2) % (PF + 1);
@@ -349,13 +359,13 @@ __global__ __launch_bounds__(64 * T3W) void pass3d_fast(Pass3D<T> a) {
       bz_l = bz_next(bz_l);
       const bool tin = t >= 0 && t < nz;
       // y-neighbours of p_k on plane t
-      sp[t & 1][w][lane] = pc;
+      sp[t & 1][w + 1][lane] = pc;
       lds_barrier();
       T s = T(0);
       const T ks = FIELD ? kc : k2c;
       {
-        const T up = (w > 0) ? sp[t & 1][w - 1][lane] : T(0);
-        const T dn = (w < T3W - 1) ? sp[t & 1][w + 1][lane] : T(0);
+        const T up = sp[t & 1][w][lane];
+        const T dn = sp[t & 1][w + 2][lane];
         const T nb = (lane_left(pc) + lane_right(pc)) + (up + dn) + (pm + pp);
         s = fma3(ks, pc, fma3(T(6), pc, -nb));
       }
@@ -371,11 +381,11 @@ __global__ __launch_bounds__(64 * T3W) void pass3d_fast(Pass3D<T> a) {
           if constexpr (NG > 1) g1acc = fma3(g1c, pc, g1acc);
         }
       }
-      srn[t & 1][w][lane] = rnew;
+      srn[t & 1][w + 1][lane] = rnew;
       // Q r_{k+1} on plane t - 1 (its y-neighbours were written last step)
       if (t - 1 >= z0 && t - 1 < z1) {
-        const T up = (w > 0) ? srn[(t - 1) & 1][w - 1][lane] : T(0);
-        const T dn = (w < T3W - 1) ? srn[(t - 1) & 1][w + 1][lane] : T(0);
+        const T up = srn[(t - 1) & 1][w][lane];
+        const T dn = srn[(t - 1) & 1][w + 2][lane];
         const T nb = (lane_left(rnm1) + lane_right(rnm1)) + (up + dn) + (rnm2 + rnew);
         const T km_t = FIELD ? km : k2c;
         const T qr = fma3(km_t, rnm1, fma3(T(6), rnm1, -nb));
@@ -423,8 +433,13 @@ __global__ __launch_bounds__(64 * T3W) void pass3d_wide(Pass3D<T> a) {
   using P2 = Pair<T>;
   constexpr int NQ = LDQ_NQ_BASE + NG;
   constexpr int PF = 4;
-  __shared__ P2 sp[2][T3W][64];
-  __shared__ P2 srn[2][T3W][64];
+  // row buffers as in pass3d_fast (rows 0 and T3W + 1 stay 0)
+  __shared__ P2 sp[2][T3W + 2][64];
+  __shared__ P2 srn[2][T3W + 2][64];
+  for (int k = threadIdx.x; k < 2 * (T3W + 2) * 64; k += blockDim.x) {
+    (&sp[0][0][0])[k] = P2{T(0), T(0)};
+    (&srn[0][0][0])[k] = P2{T(0), T(0)};
+  }
 
   const int tyz = a.tiles_y * a.nzseg;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -537,12 +552,16 @@ __global__ __launch_bounds__(64 * T3W) void pass3d_wide(Pass3D<T> a) {
   P2 rnm2 = zero, rnm1 = zero;
   int bz_m = bz_of(zs);
 
-  const int nsteps = z1 - zs;
-  for (int b = 0; b < nsteps; b += PF + 1) {
+  // steps t = zs + 1 .. z1, padded to whole pairs of rings: the extra steps store
+  // nothing and add no dot products (their planes fail the z0 <= t < z1
+  // tests), and with no exit inside the unrolled ring the compiler does not
+  // wait for every load in flight at the exit's join
+  constexpr int RING2 = 2 * (PF + 1);   // two rings per loop iteration
+  const int nsteps = (z1 - zs + RING2 - 1) / RING2 * RING2;
+  for (int b = 0; b < nsteps; b += RING2) {
 #pragma unroll
-    for (int u = 0; u < PF + 1; ++u) {
+    for (int u = 0; u < RING2; ++u) {
       const int i = b + u;
-      if (i >= nsteps) break;
       const int t = zs + 1 + i;
       const int sn = (u + 2) % (PF + 1);
       const P2 rn1 = fr[sn], pn1raw = fp[sn];
@@ -553,10 +572,10 @@ __global__ __launch_bounds__(64 * T3W) void pass3d_wide(Pass3D<T> a) {
       load_into(sn, t + PF + 2, bz_l);
       bz_l = bz_next(bz_l);
       const bool tin = t >= 0 && t < nz;
-      sp[t & 1][w][lane] = pc;
+      sp[t & 1][w + 1][lane] = pc;
       lds_barrier();
-      const P2 up = (w > 0) ? sp[t & 1][w - 1][lane] : zero;
-      const P2 dn = (w < T3W - 1) ? sp[t & 1][w + 1][lane] : zero;
+      const P2 up = sp[t & 1][w][lane];
+      const P2 dn = sp[t & 1][w + 2][lane];
       const P2 s = apply(pc, up, dn, pm, pp, FIELD ? kc : k2p);
       const bool rin = in && tin;
       const P2 rnew{rin ? fma3(-alpha_t, s.a, rc.a) : T(0), rin ? fma3(-alpha_t, s.b, rc.b) : T(0)};
@@ -572,10 +591,10 @@ __global__ __launch_bounds__(64 * T3W) void pass3d_wide(Pass3D<T> a) {
           if constexpr (NG > 1) g1acc = fma3(ma * g1c.a, pc.a, fma3(mb * g1c.b, pc.b, g1acc));
         }
       }
-      srn[t & 1][w][lane] = rnew;
+      srn[t & 1][w + 1][lane] = rnew;
       if (t - 1 >= z0 && t - 1 < z1) {
-        const P2 upr = (w > 0) ? srn[(t - 1) & 1][w - 1][lane] : zero;
-        const P2 dnr = (w < T3W - 1) ? srn[(t - 1) & 1][w + 1][lane] : zero;
+        const P2 upr = srn[(t - 1) & 1][w][lane];
+        const P2 dnr = srn[(t - 1) & 1][w + 2][lane];
         const P2 qr = apply(rnm1, upr, dnr, rnm2, rnew, FIELD ? km : k2p);
         const double ra = (double)rnm1.a, rb = (double)rnm1.b;
         q0 = __builtin_fma(ra, ra, q0);
