@@ -397,10 +397,13 @@ __global__ __launch_bounds__(256) void csr_pass_b_kernel(PassCsr<T> a) {
   }
 }
 
-// One wave per probe: reduce the partials of passes A and B, advance the base
-// CG scalars, every shift and the gradient sums (state updated in place).
-__global__ __launch_bounds__(64) void csr_tail_kernel(TailArgs ta, int ntiles, int mode) {
-  (void)pass_prologue<1>(ta, probe_ref(ta, blockIdx.x, ntiles), 0, ntiles, mode);
+// One workgroup of CSR_TAIL_W waves per probe: reduce the partials of passes
+// A and B (one per 64-row slice: thousands per probe, so the reduction is
+// spread over the workgroup, in a fixed order), advance the base CG scalars,
+// every shift and the gradient sums (state updated in place).
+constexpr int CSR_TAIL_W = 16;
+__global__ __launch_bounds__(64 * CSR_TAIL_W) void csr_tail_kernel(TailArgs ta, int ntiles, int mode) {
+  (void)pass_prologue<CSR_TAIL_W>(ta, probe_ref(ta, blockIdx.x, ntiles), 0, ntiles, mode);
 }
 
 static unsigned csr_grid(int nslices) { return (unsigned)((nslices + 3) / 4); }
@@ -471,7 +474,7 @@ hipError_t launch_csr_pass_b(const PassCsr<T> &a, int W, bool init, hipStream_t 
 
 hipError_t launch_csr_tail(const TailArgs &ta, int nprobes, int ntiles, int mode, hipStream_t st) {
   if (nprobes <= 0) return hipSuccess;
-  csr_tail_kernel<<<dim3(nprobes), dim3(64), 0, st>>>(ta, ntiles, mode);
+  csr_tail_kernel<<<dim3(nprobes), dim3(64 * CSR_TAIL_W), 0, st>>>(ta, ntiles, mode);
   return hipGetLastError();
 }
 
