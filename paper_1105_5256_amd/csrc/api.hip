@@ -55,6 +55,8 @@ template <typename T> hipError_t launch_csr_pass_a(const PassCsr<T> &, int, bool
 template <typename T> hipError_t launch_csr_pass_b(const PassCsr<T> &, int, bool, hipStream_t);
 hipError_t launch_csr_tail(const TailArgs &, int, int, int, hipStream_t);
 hipError_t launch_lanczos_check(const double *, const ProbeState *, int, int, double, double, int *, hipStream_t);
+hipError_t launch_batch_lanczos_check(const double *, const ProbeState *, int, int, const int32_t *, const double *,
+                                      int *, hipStream_t);
 template <typename T> hipError_t launch_batch2d(const Batch2D<T> &, int, bool, int, hipStream_t);
 hipError_t launch_batch_compact(const FieldDesc *, const int32_t *, int, const ProbeState *, ProbeState *, WorkItem *,
                                 int *, hipStream_t);
@@ -134,7 +136,7 @@ struct ldq_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   DevBuf vec, partials, pstate, sstate, shifts, classes, terms, stats, sums, misc, colbuf, jpkey, jpmask, hist;
-  DevBuf bfields, bitems, bwork;   // batched lattice passes
+  DevBuf bfields, bitems, bwork, blohi;   // batched lattice passes
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evp[2] = {nullptr, nullptr};   // convergence polls
   int *hpin = nullptr;                      // pinned host copies of the device counters
@@ -236,7 +238,7 @@ extern "C" void ldq_destroy(ldq_ctx *c) {
   hipStreamSynchronize(c->stream);
   for (DevBuf *b : {&c->vec, &c->partials, &c->pstate, &c->sstate, &c->shifts, &c->classes,
                     &c->terms, &c->stats, &c->sums, &c->misc, &c->colbuf, &c->jpkey, &c->jpmask, &c->hist,
-                    &c->bfields, &c->bitems, &c->bwork})
+                    &c->bfields, &c->bitems, &c->bwork, &c->blohi})
     b->release();
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
@@ -2022,14 +2024,22 @@ static int run_batched(ldq_ctx *c, std::vector<Call> &calls, double *logdet, dou
       break;
     }
   }
-  // per field: terms, enclosure check, sums (fixed order)
+  // enclosure check of every probe of every field in one launch
+  {
+    std::vector<double> lohi(2 * (size_t)nf);
+    for (int f = 0; f < nf; ++f)
+      check_interval(calls[f].lmin, calls[f].lmax, (int)sizeof(T), &lohi[2 * f], &lohi[2 * f + 1]);
+    CHK(c->blohi.reserve(lohi.size() * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(c->blohi.ptr, lohi.data(), lohi.size() * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(launch_batch_lanczos_check(ta.hist, st[1], items, hcap, c->bitems.as<int32_t>(), c->blohi.as<double>(),
+                                      c->stats.as<int>(), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));   // lohi is pageable host memory
+  }
+  // per field: terms and sums (fixed order)
   for (int f = 0; f < nf; ++f) {
     const FieldDesc &d = fd[f];
-    double clo, chi;
-    check_interval(calls[f].lmin, calls[f].lmax, (int)sizeof(T), &clo, &chi);
     int *sf = c->stats.as<int>() + (size_t)f * 8;
-    HIPCHK(launch_lanczos_check(ta.hist + (size_t)d.item_base * hcap * 2, st[1] + d.item_base, d.nprobes, hcap, clo,
-                                chi, sf, c->stream));
     double *tf = c->terms.as<double>() + (size_t)d.item_base * (1 + P);
     HIPCHK(launch_probe_terms(st[1] + d.item_base, ta.sh + (size_t)d.item_base * N, coef + (size_t)f * LDQ_MAXN,
                               d.nprobes, N, P, tf, 0, sf, c->stream));

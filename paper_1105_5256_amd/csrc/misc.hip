@@ -80,6 +80,45 @@ __global__ void lanczos_check_kernel(const double *hist, const ProbeState *st, i
   if (below + above > 0) atomicAdd(stats + 4, 1);
 }
 
+// The same check for the probes of many fields in one launch: item j
+// belongs to field item_field[j], whose interval is lohi[2 f], lohi[2 f + 1]
+// and whose count is stats[8 f + 4].
+__global__ void batch_lanczos_check_kernel(const double *hist, const ProbeState *st, int nitems, int cap,
+                                           const int32_t *item_field, const double *lohi, int *stats) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nitems) return;
+  const int f = item_field[j];
+  const double lo = lohi[2 * f], hi = lohi[2 * f + 1];
+  const int K = min(st[j].active ? st[j].iter + 1 : st[j].iter, cap);
+  const double *h = hist + (size_t)j * cap * 2;
+  double dl = 1.0, dh = 1.0, aprev = 1.0;
+  int below = 0, above = 0;
+  for (int i = 0; i < K; ++i) {
+    const double al = h[2 * i], be = h[2 * i + 1];
+    double diag = 1.0 / al, off2 = 0.0;
+    if (i > 0) {
+      diag += be / aprev;
+      off2 = be / (aprev * aprev);
+    }
+    dl = (diag - lo) - (i > 0 ? off2 / dl : 0.0);
+    dh = (hi - diag) - (i > 0 ? off2 / dh : 0.0);
+    if (dl == 0.0) dl = -1e-300;
+    if (dh == 0.0) dh = -1e-300;
+    below += dl < 0.0;
+    above += dh < 0.0;
+    aprev = al;
+  }
+  if (below + above > 0) atomicAdd(stats + 8 * f + 4, 1);
+}
+
+hipError_t launch_batch_lanczos_check(const double *hist, const ProbeState *st, int nitems, int cap,
+                                      const int32_t *item_field, const double *lohi, int *stats, hipStream_t s) {
+  if (cap <= 0 || nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_lanczos_check_kernel, dim3((nitems + 63) / 64), dim3(64), 0, s, hist, st, nitems, cap,
+                     item_field, lohi, stats);
+  return hipGetLastError();
+}
+
 hipError_t launch_lanczos_check(const double *hist, const ProbeState *st, int nprobes, int cap, double lo, double hi,
                                 int *stats, hipStream_t s) {
   if (cap <= 0 || nprobes <= 0) return hipSuccess;
