@@ -336,10 +336,31 @@ struct FastTile {
 template <typename T, int R, bool OBS, int NG, typename Prologue>
 __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prologue, double *q);
 
+// In the FP32 fast pass, workgroups 0 .. owner_blocks(nprobes) - 1 advance
+// the probes' states (one probe each, no tile) and the rest run the tiles, so
+// the per-shift recurrences run beside the tiles instead of delaying tile 0
+// (one microsecond off a 512 x 512 launch of 41 probes).  They come first so
+// that they are dispatched first; a multiple of 8 keeps the tiles' XCD
+// mapping.  The FP64 pass keeps the owner role in tile 0: its occupancy is
+// register-bound and it measured slower with the extra workgroups.
+template <typename T>
+__host__ __device__ constexpr bool sep_owner() { return sizeof(T) == 4; }
+template <typename T>
+__host__ __device__ inline int owner_blocks(int nprobes) { return sep_owner<T>() ? (nprobes + 7) & ~7 : 0; }
+
+// FP32 without observations: held to 80 VGPRs, so that 6 waves per SIMD fit
+// the 41 x 144 tiles of a 512 x 512 launch at once (the owner branch, which
+// runs once per probe, may spill a few bytes for it).
 template <typename T, int R, bool OBS, int NG>
-__global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !OBS ? 6 : 1))) void pass2d_fast(Pass2D<T> a) {
   constexpr int NQ = LDQ_NQ_BASE + NG;
-  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int nown = owner_blocks<T>(a.nprobes);
+  if ((int)blockIdx.x < nown) {
+    if ((int)blockIdx.x < a.nprobes)
+      (void)pass_prologue<1>(a.tail, probe_ref(a.tail, blockIdx.x, a.ntiles), 0, a.ntiles, MODE_STEP, ROLE_OWNER);
+    return;
+  }
+  const int L = xcd_remap(blockIdx.x - nown, gridDim.x - nown);
   const int probe = L / a.ntiles, tile = L - probe * a.ntiles;
   const ProbeRef pref = probe_ref(a.tail, probe, a.ntiles);
   const size_t off = (size_t)probe * a.nx * a.ny;
@@ -361,7 +382,9 @@ __global__ __launch_bounds__(64) void pass2d_fast(Pass2D<T> a) {
   ft.r_out = a.r_out + off;
   ft.p_out = a.p_out + off;
   double q[NQ];
-  auto prologue = [&]() { return pass_prologue<1>(a.tail, pref, tile, a.ntiles, MODE_STEP); };
+  auto prologue = [&]() {
+    return pass_prologue<1>(a.tail, pref, tile, a.ntiles, MODE_STEP, sep_owner<T>() ? ROLE_TILE : ROLE_TILE0);
+  };
   if (!fast_tile<T, R, OBS, NG>(ft, tile, prologue, q)) return;
   pass_epilogue_n<NQ>(pref, tile, a.ntiles, q);
 }
@@ -786,15 +809,15 @@ hipError_t launch_pass2d(const Pass2D<T> &a, bool squared, bool obs, bool fast, 
   if (a.mode == MODE_STEP && fast) {
     const int ng = a.tail.ngrad;
     if (squared && obs) {
-      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 2, true, 0>), dim3(nblocks), dim3(64), 0, stream, a);
-      else if (ng == 1) hipLaunchKernelGGL((pass2d_fast<T, 2, true, 1>), dim3(nblocks), dim3(64), 0, stream, a);
-      else hipLaunchKernelGGL((pass2d_fast<T, 2, true, 2>), dim3(nblocks), dim3(64), 0, stream, a);
+      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 2, true, 0>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
+      else if (ng == 1) hipLaunchKernelGGL((pass2d_fast<T, 2, true, 1>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
+      else hipLaunchKernelGGL((pass2d_fast<T, 2, true, 2>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
     } else if (squared) {
-      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 2, false, 0>), dim3(nblocks), dim3(64), 0, stream, a);
-      else hipLaunchKernelGGL((pass2d_fast<T, 2, false, 1>), dim3(nblocks), dim3(64), 0, stream, a);
+      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 2, false, 0>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
+      else hipLaunchKernelGGL((pass2d_fast<T, 2, false, 1>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
     } else {
-      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 1, false, 0>), dim3(nblocks), dim3(64), 0, stream, a);
-      else hipLaunchKernelGGL((pass2d_fast<T, 1, false, 1>), dim3(nblocks), dim3(64), 0, stream, a);
+      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 1, false, 0>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
+      else hipLaunchKernelGGL((pass2d_fast<T, 1, false, 1>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
     }
   } else if (a.mode == MODE_STEP) {
     launch_gen<T, false>(a, squared, obs, nblocks, stream);

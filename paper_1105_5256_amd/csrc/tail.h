@@ -110,41 +110,63 @@ __device__ inline bool shifts_update(const TailArgs &ta, const ProbeRef &pr, dou
   return __all(frozen);
 }
 
-// Start of a pass: reduce the previous launch's partials, advance the probe's
-// scalars, decide whether it is finished.  Called by every thread of the
-// workgroup (NW waves; one tile per workgroup).
-template <int NW>
-__device__ inline Step pass_prologue(const TailArgs &ta, const ProbeRef &pr, int tile, int ntiles, int mode) {
-  double tot[LDQ_NQ_MAX];
-  const int nq = LDQ_NQ_BASE + ta.ngrad;
-  const bool owner = (tile == 0);
-  const int nred = owner ? nq : 2;
-  // the partials are read together with the state, before the state is
-  // inspected (one memory round trip instead of two; the partial buffers are
-  // allocated for every probe, and their values are used only when the probe
-  // is active and past its first pass)
+// Who advances the probe's state in a pass: the workgroup of tile 0
+// (ROLE_TILE0), or a separate workgroup that runs no tile (ROLE_OWNER, paired
+// with ROLE_TILE for every tile workgroup, so that the per-shift recurrences
+// run beside the tiles instead of delaying tile 0).
+enum TailRole { ROLE_TILE0 = 0, ROLE_TILE = 1, ROLE_OWNER = 2 };
+
+// Whether this workgroup advances the probe's state, and how many of the
+// partial quantities it therefore reduces (the others need gamma', delta').
+__device__ inline bool tail_owner(int role, int tile) { return role == ROLE_OWNER || (role == ROLE_TILE0 && tile == 0); }
+__device__ inline int tail_nred(const TailArgs &ta, bool owner) { return owner ? LDQ_NQ_BASE + ta.ngrad : 2; }
+
+// The memory reads of a prologue: this thread's share of the previous
+// launch's partials and the probe's state.  The partials are read together
+// with the state, before the state is inspected (one memory round trip
+// instead of two; the partial buffers are allocated for every probe, and
+// their values are used only when the probe is active and past its first
+// pass).  A pass can issue these before its own first loads.
+struct PrologueIn {
   double acc[LDQ_NQ_MAX];
+  ProbeState in;
+};
+
+template <int NW>
+__device__ inline PrologueIn prologue_load(const TailArgs &ta, const ProbeRef &pr, int ntiles, int nred) {
+  PrologueIn li;
 #pragma unroll
-  for (int i = 0; i < LDQ_NQ_MAX; ++i) acc[i] = 0.0;
+  for (int i = 0; i < LDQ_NQ_MAX; ++i) li.acc[i] = 0.0;
   const double *src = pr.pin;
-  // NW = 1: one wave reduces on its own (it may be any wave of a larger workgroup)
+  // NW = 1: one wave reduces on its own (it may be any wave of a larger
+  // workgroup); tid is then the lane
   const int tid = NW == 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
   for (int t = tid; t < ntiles; t += NW * 64) {
 #pragma unroll
     for (int i = 0; i < LDQ_NQ_MAX; ++i)
-      if (i < nred) acc[i] += src[(size_t)i * ntiles + t];
+      if (i < nred) li.acc[i] += src[(size_t)i * ntiles + t];
   }
-  const ProbeState in = ta.st_in[pr.st];
+  li.in = ta.st_in[pr.st];
+  return li;
+}
+
+// The rest of a prologue, on the values prologue_load() read.
+template <int NW>
+__device__ inline Step prologue_finish(const TailArgs &ta, const ProbeRef &pr, int mode, bool owner, int nred,
+                                       const PrologueIn &li) {
+  double tot[LDQ_NQ_MAX];
+  const int tid = NW == 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+  const ProbeState in = li.in;
   Step step{false, in.colour, 0.0, 0.0};
   if (!in.active) {
-    if (tile == 0 && threadIdx.x == 0) ta.st_out[pr.st] = in;    // carry the final state forward
+    if (owner && tid == 0) ta.st_out[pr.st] = in;    // carry the final state forward
     return step;
   }
   if (mode == MODE_INIT) {
     step.run = true;
     return step;
   }
-  block_sum<NW>(acc, nred, tot);
+  block_sum<NW>(li.acc, nred, tot);
 
   ProbeState ps = in;
   bool done = false;
@@ -167,7 +189,7 @@ __device__ inline Step pass_prologue(const TailArgs &ta, const ProbeRef &pr, int
     } else {
       ps.alpha = g0 / d0;                          // alpha_0 = gamma_0 / p_0^T Q p_0 with p_0 = v
     }
-    if (owner && threadIdx.x < 64 && (int)threadIdx.x < ta.nshifts) {
+    if (owner && tid < 64 && tid < ta.nshifts) {
       ShiftState s;
       s.zeta = cmk(1.0, 0.0);
       s.zeta_prev = cmk(1.0, 0.0);
@@ -175,7 +197,7 @@ __device__ inline Step pass_prologue(const TailArgs &ta, const ProbeRef &pr, int
       s.psi = cmk(0.0, 0.0);
       s.frozen = done ? 1 : 0;
       s.pad = 0;
-      ta.sh[(size_t)pr.st * ta.nshifts + threadIdx.x] = s;
+      ta.sh[(size_t)pr.st * ta.nshifts + tid] = s;
     }
     step.alpha = ps.alpha;
     step.beta = 0.0;                               // beta_{-1} = 0: p_0 = r_0
@@ -235,7 +257,7 @@ __device__ inline Step pass_prologue(const TailArgs &ta, const ProbeRef &pr, int
     step.alpha = ps.alpha;
     step.beta = ps.beta_prev;
   }
-  if (owner && threadIdx.x == 0) {
+  if (owner && tid == 0) {
     if (done) {
       ps.active = 0;
       ps.status = status;
@@ -252,6 +274,18 @@ __device__ inline Step pass_prologue(const TailArgs &ta, const ProbeRef &pr, int
   }
   step.run = !done;
   return step;
+}
+
+// Start of a pass: reduce the previous launch's partials, advance the probe's
+// scalars, decide whether it is finished.  Called by every thread of the
+// workgroup (NW waves; one tile per workgroup).
+template <int NW>
+__device__ inline Step pass_prologue(const TailArgs &ta, const ProbeRef &pr, int tile, int ntiles, int mode,
+                                     int role = ROLE_TILE0) {
+  const bool owner = tail_owner(role, tile);
+  const int nred = tail_nred(ta, owner);
+  const PrologueIn li = prologue_load<NW>(ta, pr, ntiles, nred);
+  return prologue_finish<NW>(ta, pr, mode, owner, nred, li);
 }
 
 // End of a pass: the workgroup's sums of the nq quantities go to part_out.
