@@ -163,6 +163,12 @@ typedef struct {
                                    library's autotuner (timed once per problem shape on the context,
                                    among the specialised pass's tile and shorter tiles of the general
                                    pass) */
+  int lanes;                    /* lattices: 1 = the probes of a block advance in one chain of pass
+                                   launches; 2 = in two chains over the two halves of the block, run
+                                   concurrently on the context stream and a second stream the library
+                                   owns (each chain's fixed cost per launch overlaps the other's
+                                   streaming); 0 = chosen by the autotuner on 2-D lattices (timed
+                                   with the tile heights), 1 elsewhere.  Results are identical. */
 } ldq_options;
 
 /* launch_mode: AUTO and GRAPH capture one chunk of Krylov pass launches into a HIP graph (on a
@@ -183,8 +189,9 @@ typedef struct {
   double seconds;            /* host wall time of the call */
   double loop_seconds;       /* device time of the pass-kernel launches: HIP events on the ctx stream
                                 bracket each chunk of back-to-back launches (host polling excluded) */
-  int64_t passes;            /* Krylov iterations launched: one fused pass kernel each on lattice
-                                operators; passes A and B and the tail kernel each on CSR operators */
+  int64_t passes;            /* Krylov iterations launched: one fused pass kernel per lane each on
+                                lattice operators; passes A and B and the tail kernel each on CSR
+                                operators */
   int64_t probe_passes;      /* sum over iterations of the probes each advanced */
   double bytes_model;        /* algorithmic bytes of those passes.  Lattice: r and p read and written
                                 once per probe-site (4 x element size; the first pass writes only),
@@ -193,6 +200,9 @@ typedef struct {
                                 sliced operator and the colour array once per pass */
   int32_t enclosure_violations; /* probes whose Lanczos matrix (from their CG coefficients) has an
                                    eigenvalue outside [lambda_min, lambda_max] beyond rounding */
+  int32_t lanes;             /* lattices: concurrent chains the passes ran in (a pass is then one
+                                launch per lane, over that lane's probes); 1 otherwise */
+  int32_t tile_rows;         /* 2-D lattices: lattice rows per wave tile used; 0 otherwise */
 } ldq_info;
 
 /* ------------------------------------------------------------- the method */

@@ -42,6 +42,7 @@ class ldq_options(ctypes.Structure):
         ("check_every", ctypes.c_int),
         ("launch_mode", ctypes.c_int),
         ("tile_rows", ctypes.c_int),
+        ("lanes", ctypes.c_int),
     ]
 
 
@@ -59,6 +60,8 @@ class ldq_info(ctypes.Structure):
         ("probe_passes", ctypes.c_int64),
         ("bytes_model", ctypes.c_double),
         ("enclosure_violations", ctypes.c_int32),
+        ("lanes", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32),
     ]
 
     def as_dict(self):
