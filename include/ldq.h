@@ -164,11 +164,12 @@ typedef struct {
                                    among the specialised pass's tile and shorter tiles of the general
                                    pass) */
   int lanes;                    /* lattices: 1 = the probes of a block advance in one chain of pass
-                                   launches; 2 = in two chains over the two halves of the block, run
-                                   concurrently on the context stream and a second stream the library
-                                   owns (each chain's fixed cost per launch overlaps the other's
-                                   streaming); 0 = chosen by the autotuner on 2-D lattices (timed
-                                   with the tile heights), 1 elsewhere.  Results are identical. */
+                                   launches; 2..4 = in that many chains over near-equal shares of the
+                                   block, run concurrently on the context stream and streams the
+                                   library owns (each chain's fixed cost per launch overlaps the
+                                   others' streaming); 0 = chosen by the autotuner on 2-D lattices
+                                   (1, 2 or 3, timed with the tile heights), 1 elsewhere.  Results
+                                   are identical. */
 } ldq_options;
 
 /* launch_mode: AUTO and GRAPH capture one chunk of Krylov pass launches into a HIP graph (on a

@@ -132,6 +132,11 @@ struct DevBuf {
   template <typename T> T *as() const { return (T *)ptr; }
 };
 
+// Concurrent chains of pass launches per probe block, at most (the context
+// stream and up to three streams of the library; a process has four hardware
+// queues by default).
+constexpr int LDQ_MAX_LANES = 4;
+
 struct ldq_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -141,8 +146,9 @@ struct ldq_ctx {
   hipEvent_t evp[2] = {nullptr, nullptr};   // convergence polls
   int *hpin = nullptr;                      // pinned host copies of the device counters
   hipStream_t cap = nullptr;                // stream for HIP graph capture (created on first use)
-  hipStream_t lane1 = nullptr;              // second chain of pass launches (created on first use)
-  hipEvent_t evf = nullptr, evj = nullptr;  // fork to and join from lane1
+  hipStream_t lane[LDQ_MAX_LANES] = {};     // lanes 1.. of the pass launches (created on first use)
+  hipEvent_t evf = nullptr;                 // fork of the lanes from the context stream
+  hipEvent_t evj[LDQ_MAX_LANES] = {};       // join of lane l back to it
   std::map<std::string, int> tuned_rows;    // autotuner choices for 2-D lattice problems (rows, lanes)
   std::vector<double> last_terms;
   int last_nparams = 0;
@@ -247,12 +253,14 @@ extern "C" void ldq_destroy(ldq_ctx *c) {
   for (hipEvent_t e : c->evp)
     if (e) hipEventDestroy(e);
   if (c->cap) hipStreamDestroy(c->cap);
-  if (c->lane1) {
-    hipStreamSynchronize(c->lane1);
-    hipStreamDestroy(c->lane1);
-  }
+  for (hipStream_t s : c->lane)
+    if (s) {
+      hipStreamSynchronize(s);
+      hipStreamDestroy(s);
+    }
   if (c->evf) hipEventDestroy(c->evf);
-  if (c->evj) hipEventDestroy(c->evj);
+  for (hipEvent_t e : c->evj)
+    if (e) hipEventDestroy(e);
   if (c->hpin) hipHostFree(c->hpin);
   delete c;
 }
@@ -864,7 +872,7 @@ struct Call {
   int ntiles;
   int stats[8];
   int rows2d;        // 2-D lattices: rows per wave tile (0: the specialised pass's standard tile)
-  int lanes;         // lattices: concurrent chains of pass launches per probe block (1 or 2)
+  int lanes;         // lattices: concurrent chains of pass launches per probe block (1..LDQ_MAX_LANES)
   double *tune_ms;   // non-null: a timing run of the autotuner (a few passes of the first probe block)
 };
 
@@ -991,12 +999,15 @@ static int graph_chunk(ldq_ctx *c, ChunkGraph &g, F enqueue_on, hipStream_t on) 
   return LDQ_OK;
 }
 
-// The second chain of pass launches and the events that fork it from and join
-// it to the context stream (default priority, like the context stream).
-static int ensure_lane1(ldq_ctx *c) {
-  if (!c->lane1) HIPCHK(hipStreamCreateWithFlags(&c->lane1, hipStreamNonBlocking));
+// Streams of lanes 1 .. nlanes - 1 of the pass launches and the events that
+// fork them from and join them to the context stream (default priority, like
+// the context stream; lane 0 is the context stream itself).
+static int ensure_lanes(ldq_ctx *c, int nlanes) {
+  for (int l = 1; l < nlanes; ++l) {
+    if (!c->lane[l]) HIPCHK(hipStreamCreateWithFlags(&c->lane[l], hipStreamNonBlocking));
+    if (!c->evj[l]) HIPCHK(hipEventCreateWithFlags(&c->evj[l], hipEventDisableTiming));
+  }
   if (!c->evf) HIPCHK(hipEventCreateWithFlags(&c->evf, hipEventDisableTiming));
-  if (!c->evj) HIPCHK(hipEventCreateWithFlags(&c->evj, hipEventDisableTiming));
   return LDQ_OK;
 }
 
@@ -1257,23 +1268,28 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     HIPCHK(launch(MODE_FIRST, nb, 0, nullptr, nullptr, bufA_r, bufA_p));
     passes += 2;
     // the STEP passes of the block in nlanes chains: lane l advances probes
-    // lp0[l] .. lp0[l] + lnp[l] - 1; lane 1 runs on its own stream, forked from
-    // and joined to the context stream around every chunk
-    const int nlanes = (k.lanes == 2 && nb >= 2) ? 2 : 1;
-    const int lnp[2] = {nlanes == 2 ? (nb + 1) / 2 : nb, nlanes == 2 ? nb / 2 : 0};
-    const int lp0[2] = {0, lnp[0]};
-    if (nlanes == 2) CHK(ensure_lane1(c));
+    // lp0[l] .. lp0[l] + lnp[l] - 1 (near-equal shares); lanes 1.. run on
+    // streams of their own, forked from and joined to the context stream
+    // around every chunk
+    const int nlanes = std::max(1, std::min(k.lanes, nb));
+    int lnp[LDQ_MAX_LANES] = {}, lp0[LDQ_MAX_LANES] = {};
+    for (int l = 0; l < nlanes; ++l) {
+      lnp[l] = nb / nlanes + (l < nb % nlanes ? 1 : 0);
+      lp0[l] = l ? lp0[l - 1] + lnp[l - 1] : 0;
+    }
+    auto lane_stream = [&](int l) { return l ? c->lane[l] : c->stream; };
+    if (nlanes > 1) CHK(ensure_lanes(c, nlanes));
     auto fork = [&]() -> int {
-      if (nlanes == 2) {
+      if (nlanes > 1) {
         HIPCHK(hipEventRecord(c->evf, c->stream));
-        HIPCHK(hipStreamWaitEvent(c->lane1, c->evf, 0));
+        for (int l = 1; l < nlanes; ++l) HIPCHK(hipStreamWaitEvent(c->lane[l], c->evf, 0));
       }
       return LDQ_OK;
     };
     auto join = [&]() -> int {
-      if (nlanes == 2) {
-        HIPCHK(hipEventRecord(c->evj, c->lane1));
-        HIPCHK(hipStreamWaitEvent(c->stream, c->evj, 0));
+      for (int l = 1; l < nlanes; ++l) {
+        HIPCHK(hipEventRecord(c->evj[l], c->lane[l]));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->evj[l], 0));
       }
       return LDQ_OK;
     };
@@ -1284,7 +1300,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
       HIPCHK(hipEventRecord(c->ev0, c->stream));
       CHK(fork());
       for (int l = 0; l < nlanes; ++l) {
-        ls = l ? c->lane1 : c->stream;
+        ls = lane_stream(l);
         for (int i = 0; i < TUNE_STEPS; ++i)
           HIPCHK(i % 2 == 0 ? launch(MODE_STEP, lnp[l], 1, bufA_r, bufA_p, bufB_r, bufB_p, lp0[l])
                             : launch(MODE_STEP, lnp[l], 0, bufB_r, bufB_p, bufA_r, bufA_p, lp0[l]));
@@ -1316,11 +1332,11 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
       ls = c->stream;
       return LDQ_OK;
     };
-    ChunkGraph cg[2];
+    ChunkGraph cg[LDQ_MAX_LANES];
     auto chunk = [&]() -> int {
       CHK(fork());
       for (int l = 0; l < nlanes; ++l) {
-        hipStream_t on = l ? c->lane1 : c->stream;
+        hipStream_t on = lane_stream(l);
         auto lane_steps = [&](hipStream_t s) { return steps(l, s); };
         CHK(graphs ? graph_chunk(c, cg[l], lane_steps, on) : steps(l, on));
       }
@@ -1343,7 +1359,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   int64_t iters_total = 0;
   CHK(collect_results(k, nprobes_total, kernel_ms, passes, info, out_sums, &iters_total));
   if (info) {
-    info->lanes = (k.lanes == 2 && block >= 2) ? 2 : 1;
+    info->lanes = std::max(1, std::min(k.lanes, block));
     info->tile_rows = is3d ? 0 : rows2d;
     // vectors: first pass writes r, p; every later pass reads and writes both;
     // operator fields (kappa2 / derivative diagonals / observation planes) once per launch
@@ -1738,7 +1754,8 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
   if (!(k.o.tol > 0.0) || !(k.o.grad_tol >= 0.0) || k.o.max_iter < 1)
     return fail(LDQ_E_INVALID, "tol must be > 0, grad_tol >= 0, max_iter >= 1");
   if (k.o.precision != LDQ_FP64 && k.o.precision != LDQ_MIXED) return fail(LDQ_E_INVALID, "unknown precision");
-  if (k.o.lanes < 0 || k.o.lanes > 2) return fail(LDQ_E_INVALID, "lanes must be 0, 1 or 2");
+  if (k.o.lanes < 0 || k.o.lanes > LDQ_MAX_LANES)
+    return fail(LDQ_E_INVALID, "lanes must be in 0..%d", LDQ_MAX_LANES);
   if (Q->kind != OPK_LATTICE && Q->kind != OPK_CSR)
     return fail(LDQ_E_UNSUPPORTED, "the Krylov passes are implemented for lattice and CSR operators");
   if (Q->kind == OPK_LATTICE && Q->ndim == 2 && nparams > 2)
@@ -1816,7 +1833,7 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
 static int tune_rows(Call &k) {
   ldq_op *Q = k.Q;
   k.rows2d = 0;
-  k.lanes = k.o.lanes == 2 ? 2 : 1;
+  k.lanes = k.o.lanes > 0 ? k.o.lanes : 1;
   if (Q->ndim != 2) return LDQ_OK;
   const bool sq = Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN;
   if (k.o.tile_rows > 0) {
@@ -1833,12 +1850,14 @@ static int tune_rows(Call &k) {
     k.lanes = it->second / 1000;
     return LDQ_OK;
   }
-  // two lanes are timed against one wherever a block has two probes or more
-  // (they measured 2-10 % faster on 512 x 512 blocks of 13 to 61 probes)
+  // two and three lanes are timed against one wherever a block has that many
+  // probes (two measured 2-10 % faster on 512 x 512 blocks of 13 to 61 probes)
   const int nprobes = (int)k.classes.size();
   const int block = (k.o.probe_block > 0) ? std::min(k.o.probe_block, nprobes) : nprobes;
-  int lane_cands[2] = {k.lanes, 0};
-  if (k.o.lanes == 0 && block >= 2) lane_cands[1] = 2;
+  int lane_cands[3] = {k.lanes, 0, 0};
+  if (k.o.lanes == 0)
+    for (int l = 2; l <= 3; ++l)
+      if (block >= l) lane_cands[l - 1] = l;
   const int cands[4] = {LDQ_ROWS2D, 4, 9, 16};
   int best = 0, best_lanes = 1;
   double best_ms = 0.0;

@@ -248,8 +248,8 @@ def test_graph_and_direct_launches_agree(ctx, shape, kind, k, precision):
         assert np.array_equal(r[3], res[0][3])
 
 
-# two concurrent lanes (halves of each probe block on two streams) change
-# nothing: every probe runs the same arithmetic, the terms are summed in probe
+# concurrent lanes (shares of each probe block on two to four streams)
+# change nothing: every probe runs the same arithmetic, the terms are summed in probe
 # order.  Odd blocks (unequal halves), several blocks, several chunks; the
 # standard and a short tile; 2-D fast and general passes, 3-D wide and strip
 # passes; graph-replayed and direct launches.
@@ -267,15 +267,17 @@ def test_two_lanes_agree(ctx, shape, kind, k, precision, rows):
         if kind == ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN else ctx.op(ldq.ldq_op_diag(ctx.handle, np.linspace(0.5, 1.5, n)))
     res = []
     for lanes, block, mode in ((1, 0, ldq.LDQ_LAUNCH_AUTO), (2, 0, ldq.LDQ_LAUNCH_AUTO), (2, 0, ldq.LDQ_LAUNCH_DIRECT),
-                               (1, 7, ldq.LDQ_LAUNCH_AUTO), (2, 7, ldq.LDQ_LAUNCH_GRAPH)):
+                               (1, 7, ldq.LDQ_LAUNCH_AUTO), (2, 7, ldq.LDQ_LAUNCH_GRAPH), (3, 0, ldq.LDQ_LAUNCH_AUTO),
+                               (4, 7, ldq.LDQ_LAUNCH_DIRECT)):
         opts = ldq.ldq_options_default(k=k, tol=1e-6, grad_tol=1e-7, precision=precision, probe_block=block,
                                        check_every=6, launch_mode=mode, lanes=lanes, tile_rows=rows)
         v, g, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
         res.append((v, g[0], info["iters_total"], ldq.ldq_probe_terms(ctx.handle)))
-    for i in (1, 2):
+    for i in (1, 2, 5):
         assert res[i][0] == res[0][0] and res[i][1] == res[0][1] and res[i][2] == res[0][2], i
         assert np.array_equal(res[i][3], res[0][3]), i
-    assert res[4][0] == res[3][0] and res[4][1] == res[3][1] and np.array_equal(res[4][3], res[3][3])
+    for i in (4, 6):
+        assert res[i][0] == res[3][0] and res[i][1] == res[3][1] and np.array_equal(res[i][3], res[3][3]), i
     # blocks of 7 change only the order in which the probes are run
     assert abs(res[3][0] - res[0][0]) <= 1e-12 * abs(res[0][0])
 
@@ -287,11 +289,12 @@ def test_lanes_autotuned(ctx):
     Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, 0.05))
     dQ = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, 0.05, scale=2.0))
     out = {}
-    for lanes in (0, 1, 2):
+    for lanes in (0, 1, 2, 3):
         opts = ldq.ldq_options_default(k=4, tol=1e-5, grad_tol=1e-5, precision=ldq.LDQ_MIXED, lanes=lanes)
-        v, g, _ = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
+        v, g, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
         out[lanes] = (v, g[0])
-    assert out[2] == out[1]
+        assert info["lanes"] == (lanes if lanes else info["lanes"]) and 1 <= info["lanes"] <= 3
+    assert out[2] == out[1] and out[3] == out[1]
     assert rel(out[0][0], out[1][0]) < 1e-12 and rel(out[0][1], out[1][1]) < 1e-11
 
 
@@ -359,7 +362,7 @@ def test_error_paths(ctx):
     with pytest.raises(ldq.LdqError) as e:
         ldq.ldq_logdet(ctx.handle, Q, ldq.ldq_options_default(k=2, nshifts=0))
     assert e.value.status == ldq.LDQ_E_INVALID
-    for lanes in (-1, 3):
+    for lanes in (-1, 5):
         with pytest.raises(ldq.LdqError) as e:
             ldq.ldq_logdet(ctx.handle, Q, ldq.ldq_options_default(k=2, lanes=lanes))
         assert e.value.status == ldq.LDQ_E_INVALID
