@@ -356,7 +356,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if w.timed == ldq.LDQ_MIXED else "f64",
         "data": "synthetic",
         "config": {"workload": w.describe, "n": w.n, "probes": sum(i["ncolours"] for i in one_eval),
                    "nshifts": 20, "tol": w.tol, "grad_tol": w.gtol,

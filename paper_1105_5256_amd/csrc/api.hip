@@ -2077,6 +2077,7 @@ static int run_batched(ldq_ctx *c, std::vector<Call> &calls, double *logdet, dou
   }
   Batch2D<T> b{};
   b.work = c->bwork.as<WorkItem>();
+  b.count = counter;
   b.fields = c->bfields.as<FieldDesc>();
   b.sigma = sig;
   b.rows = rows;
@@ -2106,8 +2107,13 @@ static int run_batched(ldq_ctx *c, std::vector<Call> &calls, double *logdet, dou
   int64_t launches = 2 * (int64_t)nf, steps = 0;
   int64_t tiles_run = 0;
   bool stalled = false;
-  while (nwork > 0) {
-    HIPCHK(hipEventRecord(c->ev0, c->stream));
+  // A chunk of passes over the work list: replayed from a graph captured for a
+  // grid of `grid` workgroups, which serves while the list (whose live length
+  // the kernel reads from the device) is between half that and that long;
+  // below half, the chunk is captured again with the current length.
+  const bool graphs = k0.o.launch_mode != LDQ_LAUNCH_DIRECT;
+  int grid = 0;
+  auto chunk_steps = [&](hipStream_t s) -> int {
     for (int i = 0; i < check; ++i) {
       const int in = (i % 2 == 0) ? 1 : 0;
       b.tail.st_in = st[in];
@@ -2118,7 +2124,24 @@ static int run_batched(ldq_ctx *c, std::vector<Call> &calls, double *logdet, dou
       b.p_in = in ? bufA_p : bufB_p;
       b.r_out = in ? bufB_r : bufA_r;
       b.p_out = in ? bufB_p : bufA_p;
-      HIPCHK(launch_batch2d<T>(b, nwork, sq, P, c->stream));
+      const hipError_t e = launch_batch2d<T>(b, grid, sq, P, s);
+      if (e != hipSuccess) return fail(LDQ_E_DEVICE, "batched pass launch: %s", hipGetErrorString(e));
+    }
+    return LDQ_OK;
+  };
+  ChunkGraph bg;
+  while (nwork > 0) {
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
+    if (graphs) {
+      if (nwork > grid || 2 * nwork < grid) {
+        if (bg.exec) HIPCHK(hipGraphExecDestroy(bg.exec));
+        bg.exec = nullptr;
+        grid = nwork;
+      }
+      CHK(graph_chunk(c, bg, chunk_steps, c->stream));
+    } else {
+      grid = nwork;
+      CHK(chunk_steps(c->stream));
     }
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     launches += check;

@@ -161,6 +161,7 @@ struct WorkItem {
 template <typename T>
 struct Batch2D {
   const WorkItem *work;
+  const int *count;     // live length of the work list (device; the grid may be longer)
   const FieldDesc *fields;
   const cplx *sigma;    // [field][LDQ_MAXN]
   int rows, colC, cola;

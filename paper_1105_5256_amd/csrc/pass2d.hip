@@ -707,7 +707,12 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
 template <typename T, int R, int NG>
 __global__ __launch_bounds__(64) void batch2d_fast(Batch2D<T> b) {
   constexpr int NQ = LDQ_NQ_BASE + NG;
-  const WorkItem wk = b.work[xcd_remap(blockIdx.x, gridDim.x)];
+  // the grid was sized for a work list at least this long (a replayed graph
+  // keeps its grid while the list shrinks); workgroups beyond it leave, the
+  // rest are spread over the XCDs as for a grid of exactly `cnt`
+  const int cnt = *b.count;
+  if ((int)blockIdx.x >= cnt) return;
+  const WorkItem wk = b.work[xcd_remap(blockIdx.x, cnt)];
   const FieldDesc fd = b.fields[wk.field];
   const size_t po = (size_t)fd.part_off + (size_t)wk.probe * NQ * fd.ntiles;
   const ProbeRef pref{fd.item_base + wk.probe, b.tail.part_in + po, b.tail.part_out + po,

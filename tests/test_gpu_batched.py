@@ -81,6 +81,24 @@ def test_batched_equals_single_calls_and_oracle(ctx, precision, tol, gtol, bound
     assert first == terms.shape[0]
 
 
+# graph-replayed chunks (captured again whenever the work list falls below
+# half the captured grid) against launches enqueued one by one: identical
+def test_batched_graph_and_direct_agree(ctx):
+    wl = workloads.batch2d(nfields=12, side_lo=8, side_hi=96, seed=3)
+    say(f"batched graph vs direct, {len(wl['fields'])} fields")
+    Qs, dQs = make_fields(ctx, wl["fields"])
+    res = []
+    for mode in (ldq.LDQ_LAUNCH_DIRECT, ldq.LDQ_LAUNCH_GRAPH, ldq.LDQ_LAUNCH_AUTO):
+        opts = ldq.ldq_options_default(k=4, nshifts=20, tol=1e-5, grad_tol=1e-6, precision=ldq.LDQ_MIXED,
+                                       check_every=4, launch_mode=mode)
+        vals, grads, infos = ldq.ldq_logdet_batched(ctx.handle, Qs, dQs, opts)
+        res.append((list(vals), [g[0] for g in grads], [i["iters_total"] for i in infos],
+                    ldq.ldq_probe_terms(ctx.handle)))
+    for r in res[1:]:
+        assert r[0] == res[0][0] and r[1] == res[0][1] and r[2] == res[0][2]
+        assert np.array_equal(r[3], res[0][3])
+
+
 def test_batched_falls_back_for_mixed_operator_kinds(ctx):
     say("batched call with a lattice field and a CSR field (per-field path)")
     f = dict(shape=(30, 20), kappa2=0.3)
