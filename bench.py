@@ -94,10 +94,10 @@ class Workload:
                              "modular colouring (41 probes), N=20 shifts, log det + d/dkappa2")
             self.kernel = "pass2d_fast<float, R=2, no observations, 1 gradient> (fused 2-D pass)"
             self.n = 512 * 512
-            # two concurrent lanes of 21 and 20 probes in the mixed form: the autotuner's choice here,
-            # fixed so that a run under the profiler (which slows the tuner's short timing runs
-            # unevenly) makes the same choice
-            self.lanes = {L.LDQ_MIXED: 2}
+            # two concurrent lanes of 21 and 20 probes and the standard 34-row tile in the mixed
+            # form: the autotuner's choice here, fixed so that a run under the profiler (which slows
+            # the tuner's short timing runs unevenly) makes the same choice
+            self.pin = {L.LDQ_MIXED: dict(lanes=2, tile_rows=34)}
         elif name == "lattice64_5pt":
             wl = workloads.lattice2d_5pt(64, 0.1, 2)
             self.wl = wl
@@ -156,7 +156,7 @@ class Workload:
     def opts(self, precision, tol, gtol):
         from paper_1105_5256_amd import ldq
         return ldq.ldq_options_default(k=self.k, nshifts=20, tol=tol, grad_tol=gtol, precision=precision,
-                                       lanes=getattr(self, "lanes", {}).get(precision, 0))
+                                       **getattr(self, "pin", {}).get(precision, {}))
 
     def run(self, opts):
         """One evaluation: (values, gradients, list of info dicts)."""

@@ -1858,14 +1858,17 @@ static int tune_rows(Call &k) {
   if (k.o.lanes == 0)
     for (int l = 2; l <= 3; ++l)
       if (block >= l) lane_cands[l - 1] = l;
-  const int cands[4] = {LDQ_ROWS2D, 4, 9, 16};
+  // the specialised pass's standard tile, its tall tile (FP32), and shorter
+  // tiles of the general pass
+  const int cands[5] = {LDQ_ROWS2D, LDQ_ROWS2D_TALL, 4, 9, 16};
   int best = 0, best_lanes = 1;
   double best_ms = 0.0;
   for (int lanes : lane_cands) {
     if (lanes == 0) continue;
     for (int want : cands) {
       const int rows = pass2d_rows(sq, want);
-      if (want != LDQ_ROWS2D && rows >= pass2d_rows(sq, LDQ_ROWS2D)) continue;
+      if (want == LDQ_ROWS2D_TALL && k.o.precision != LDQ_MIXED) continue;
+      if (want != LDQ_ROWS2D && want != LDQ_ROWS2D_TALL && rows >= pass2d_rows(sq, LDQ_ROWS2D)) continue;
       // the faster of two timing runs of each candidate
       double ms = 0.0;
       k.rows2d = rows;
@@ -1971,7 +1974,9 @@ static int run_batched(ldq_ctx *c, std::vector<Call> &calls, double *logdet, dou
   const int N = k0.o.nshifts;
   const int nq = LDQ_NQ_BASE + P;
   const bool sq = k0.Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN;
-  const int rows = pass2d_rows(sq, LDQ_ROWS2D);
+  // the batched pass runs the standard tile or, in FP32, the tall one
+  const bool tall = sizeof(T) == 4 && k0.rows2d == pass2d_rows(sq, LDQ_ROWS2D_TALL);
+  const int rows = pass2d_rows(sq, tall ? LDQ_ROWS2D_TALL : LDQ_ROWS2D);
   std::vector<FieldDesc> fd(nf);
   std::vector<int32_t> item_field, classes;
   int64_t vec_tot = 0, part_tot = 0, work_max = 0;
@@ -2223,6 +2228,8 @@ static int run_batched(ldq_ctx *c, std::vector<Call> &calls, double *logdet, dou
       o.passes = launches;
       o.probe_passes = o.iters_total;
       o.bytes_model = bytes[f];
+      o.lanes = 1;
+      o.tile_rows = rows;
     }
   }
   (void)tiles_run;
@@ -2249,6 +2256,9 @@ extern "C" int ldq_logdet_batched(ldq_ctx *c, int nfields, const ldq_op *const *
       ok = calls[f].o.precision == calls[0].o.precision;
     }
     if (ok && batchable(calls)) {
+      // tile height: the option when it names the standard or the tall tile
+      if (calls[0].o.tile_rows > 0)
+        calls[0].rows2d = pass2d_rows(calls[0].Q->lkind == LDQ_SQUARED_SHIFTED_LAPLACIAN, calls[0].o.tile_rows);
       const int st = calls[0].o.precision == LDQ_MIXED ? run_batched<float>(c, calls, logdet, grad, info)
                                                        : run_batched<double>(c, calls, logdet, grad, info);
       const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

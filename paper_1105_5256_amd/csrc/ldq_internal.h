@@ -8,8 +8,9 @@
 #define LDQ_MAXN 64         // shifts per call (one wave64 lane per shift)
 #define LDQ_BLOCK 256       // threads per workgroup of the pass kernels
 #ifndef LDQ_ROWS2D
-#define LDQ_ROWS2D 32      // rows per wave tile of the 2-D pass (rounded up so that rows + 4R is a multiple of 5)
+#define LDQ_ROWS2D 32      // rows per wave tile of the 2-D pass (rounded up so that rows + 2R + 2 is a multiple of 5)
 #endif
+#define LDQ_ROWS2D_TALL 64  // rows of the tall tile of the FP32 fast 2-D passes (rounded up the same way)
 #define LDQ_NQ_BASE 3       // reduced quantities of a pass: gamma, delta, rho (+ one omega per parameter)
 
 namespace ldq {

@@ -333,7 +333,7 @@ struct FastTile {
   T *r_out, *p_out;    // the probe's vectors
 };
 
-template <typename T, int R, bool OBS, int NG, typename Prologue>
+template <typename T, int R, bool OBS, int NG, int TR, typename Prologue>
 __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prologue, double *q);
 
 // In the FP32 fast pass, workgroups 0 .. owner_blocks(nprobes) - 1 advance
@@ -351,7 +351,7 @@ __host__ __device__ inline int owner_blocks(int nprobes) { return sep_owner<T>()
 // FP32 without observations: held to 80 VGPRs, so that 6 waves per SIMD fit
 // the 41 x 144 tiles of a 512 x 512 launch at once (the owner branch, which
 // runs once per probe, may spill a few bytes for it).
-template <typename T, int R, bool OBS, int NG>
+template <typename T, int R, bool OBS, int NG, int TR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !OBS ? 6 : 1))) void pass2d_fast(Pass2D<T> a) {
   constexpr int NQ = LDQ_NQ_BASE + NG;
   const int nown = owner_blocks<T>(a.nprobes);
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   auto prologue = [&]() {
     return pass_prologue<1>(a.tail, pref, tile, a.ntiles, MODE_STEP, sep_owner<T>() ? ROLE_TILE : ROLE_TILE0);
   };
-  if (!fast_tile<T, R, OBS, NG>(ft, tile, prologue, q)) return;
+  if (!fast_tile<T, R, OBS, NG, TR>(ft, tile, prologue, q)) return;
   pass_epilogue_n<NQ>(pref, tile, a.ntiles, q);
 }
 
@@ -397,13 +397,22 @@ constexpr int rows_full() {
   while ((r + 2 * R + 2) % 5 != 0) ++r;
   return r;
 }
+// Rows of the tall tile of the FP32 fast passes (64 rounded up the same way):
+// fewer halo rows re-read per row of output (6 per 64 instead of 6 per 34),
+// which pays where the vectors stream from HBM.
+template <int R>
+constexpr int rows_tall() {
+  int r = LDQ_ROWS2D_TALL;
+  while ((r + 2 * R + 2) % 5 != 0) ++r;
+  return r;
+}
 
 // One tile of one probe: the march of the fused pass; q[] receives this
 // wave's sums of the pass's dot products.  The first rows of r and p are
 // requested before prologue() (the reduction of the previous launch's
 // partials, which yields alpha, beta and the probe's colour) so that its
 // memory round trips overlap; returns false when the probe is not active.
-template <typename T, int R, bool OBS, int NG, typename Prologue>
+template <typename T, int R, bool OBS, int NG, int TR, typename Prologue>
 __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prologue, double *q) {
   constexpr int H = R + 1;
   constexpr int W = 64 - 2 * H;
@@ -474,7 +483,7 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
 
   auto march = [&](auto interior_tag) {
     constexpr bool IN = decltype(interior_tag)::value;
-    constexpr int RF = rows_full<R>();
+    constexpr int RF = TR;   // the tile's rows (a.rows == TR: checked by the launchers)
     constexpr int NFULL = RF + 2 * H;
     // (colour - a (y - 1)) mod C for the gradient row y - 1 of step 0
     int tg;
@@ -704,7 +713,7 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
 }
 
 // Batched STEP pass: one wave per work-list entry (field, probe, tile).
-template <typename T, int R, int NG>
+template <typename T, int R, int NG, int TR>
 __global__ __launch_bounds__(64) void batch2d_fast(Batch2D<T> b) {
   constexpr int NQ = LDQ_NQ_BASE + NG;
   // the grid was sized for a work list at least this long (a replayed graph
@@ -737,20 +746,32 @@ __global__ __launch_bounds__(64) void batch2d_fast(Batch2D<T> b) {
   ft.p_out = b.p_out + off;
   double q[NQ];
   auto prologue = [&]() { return pass_prologue<1>(b.tail, pref, wk.tile, fd.ntiles, MODE_STEP); };
-  if (!fast_tile<T, R, false, NG>(ft, wk.tile, prologue, q)) return;
+  if (!fast_tile<T, R, false, NG, TR>(ft, wk.tile, prologue, q)) return;
   pass_epilogue_n<NQ>(pref, wk.tile, fd.ntiles, q);
 }
 
+template <typename T, int R, int TR>
+static void launch_batch_ng(const Batch2D<T> &b, int ngrad, int grid, hipStream_t stream) {
+  if (ngrad == 0) hipLaunchKernelGGL((batch2d_fast<T, R, 0, TR>), dim3(grid), dim3(64), 0, stream, b);
+  else hipLaunchKernelGGL((batch2d_fast<T, R, 1, TR>), dim3(grid), dim3(64), 0, stream, b);
+}
+
+// b.rows is the standard tile height or (FP32) the tall one.
 template <typename T>
 hipError_t launch_batch2d(const Batch2D<T> &b, int nwork, bool squared, int ngrad, hipStream_t stream) {
   if (nwork <= 0) return hipSuccess;
-  if (squared) {
-    if (ngrad == 0) hipLaunchKernelGGL((batch2d_fast<T, 2, 0>), dim3(nwork), dim3(64), 0, stream, b);
-    else hipLaunchKernelGGL((batch2d_fast<T, 2, 1>), dim3(nwork), dim3(64), 0, stream, b);
-  } else {
-    if (ngrad == 0) hipLaunchKernelGGL((batch2d_fast<T, 1, 0>), dim3(nwork), dim3(64), 0, stream, b);
-    else hipLaunchKernelGGL((batch2d_fast<T, 1, 1>), dim3(nwork), dim3(64), 0, stream, b);
+  if constexpr (sizeof(T) == 4) {
+    if (squared && b.rows == rows_tall<2>()) {
+      launch_batch_ng<T, 2, rows_tall<2>()>(b, ngrad, nwork, stream);
+      return hipGetLastError();
+    }
+    if (!squared && b.rows == rows_tall<1>()) {
+      launch_batch_ng<T, 1, rows_tall<1>()>(b, ngrad, nwork, stream);
+      return hipGetLastError();
+    }
   }
+  if (squared) launch_batch_ng<T, 2, rows_full<2>()>(b, ngrad, nwork, stream);
+  else launch_batch_ng<T, 1, rows_full<1>()>(b, ngrad, nwork, stream);
   return hipGetLastError();
 }
 template hipError_t launch_batch2d<float>(const Batch2D<float> &, int, bool, int, hipStream_t);
@@ -806,24 +827,34 @@ static void launch_gen(const Pass2D<T> &a, bool squared, bool obs, int nblocks, 
 
 // ngrad <= 2 (checked by the host driver for 2-D lattices); a.rows + 2H must
 // be a multiple of 5 (pass2d_rows).
+template <typename T, int R, bool OBS, int TR>
+static void launch_fast_ng(const Pass2D<T> &a, int ng, hipStream_t stream) {
+  const dim3 g(a.ntiles * a.nprobes + owner_blocks<T>(a.nprobes));
+  if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, R, OBS, 0, TR>), g, dim3(64), 0, stream, a);
+  else if (ng == 1 || !OBS) hipLaunchKernelGGL((pass2d_fast<T, R, OBS, 1, TR>), g, dim3(64), 0, stream, a);
+  else hipLaunchKernelGGL((pass2d_fast<T, R, OBS, OBS ? 2 : 1, TR>), g, dim3(64), 0, stream, a);
+}
+
+template <typename T, int TR2, int TR1>
+static void launch_fast(const Pass2D<T> &a, bool squared, bool obs, hipStream_t stream) {
+  const int ng = a.tail.ngrad;
+  if (squared && obs) launch_fast_ng<T, 2, true, TR2>(a, ng, stream);
+  else if (squared) launch_fast_ng<T, 2, false, TR2>(a, ng, stream);
+  else launch_fast_ng<T, 1, false, TR1>(a, ng, stream);
+}
+
+// ngrad <= 2 (checked by the host driver for 2-D lattices); a.rows + 2H must
+// be a multiple of 5 (pass2d_rows).  The fast pass runs tiles of the standard
+// height, and in FP32 also of the tall height.
 template <typename T>
 hipError_t launch_pass2d(const Pass2D<T> &a, bool squared, bool obs, bool fast, hipStream_t stream) {
   const int nblocks = a.ntiles * a.nprobes;
-  // the fast pass assumes tiles of the standard height
-  fast = fast && a.rows == (squared ? rows_full<2>() : rows_full<1>());
-  if (a.mode == MODE_STEP && fast) {
-    const int ng = a.tail.ngrad;
-    if (squared && obs) {
-      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 2, true, 0>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
-      else if (ng == 1) hipLaunchKernelGGL((pass2d_fast<T, 2, true, 1>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
-      else hipLaunchKernelGGL((pass2d_fast<T, 2, true, 2>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
-    } else if (squared) {
-      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 2, false, 0>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
-      else hipLaunchKernelGGL((pass2d_fast<T, 2, false, 1>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
-    } else {
-      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, 1, false, 0>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
-      else hipLaunchKernelGGL((pass2d_fast<T, 1, false, 1>), dim3(nblocks + owner_blocks<T>(a.nprobes)), dim3(64), 0, stream, a);
-    }
+  const bool std_rows = a.rows == (squared ? rows_full<2>() : rows_full<1>());
+  const bool tall_rows = sizeof(T) == 4 && a.rows == (squared ? rows_tall<2>() : rows_tall<1>());
+  if (a.mode == MODE_STEP && fast && std_rows) {
+    launch_fast<T, rows_full<2>(), rows_full<1>()>(a, squared, obs, stream);
+  } else if (a.mode == MODE_STEP && fast && tall_rows) {
+    if constexpr (sizeof(T) == 4) launch_fast<T, rows_tall<2>(), rows_tall<1>()>(a, squared, obs, stream);
   } else if (a.mode == MODE_STEP) {
     launch_gen<T, false>(a, squared, obs, nblocks, stream);
   } else {

@@ -99,6 +99,22 @@ def test_batched_graph_and_direct_agree(ctx):
         assert np.array_equal(r[3], res[0][3])
 
 
+# the tall tile in the batched pass (FP32) against the standard tile
+def test_batched_tall_tile(ctx):
+    wl = workloads.batch2d(nfields=10, side_lo=20, side_hi=140, seed=4)
+    say(f"batched tall tile, {len(wl['fields'])} fields")
+    Qs, dQs = make_fields(ctx, wl["fields"])
+    out = {}
+    for rows in (0, 64):
+        opts = ldq.ldq_options_default(k=4, nshifts=20, tol=1e-6, grad_tol=1e-7, precision=ldq.LDQ_MIXED,
+                                       tile_rows=rows)
+        vals, grads, infos = ldq.ldq_logdet_batched(ctx.handle, Qs, dQs, opts)
+        assert infos[0]["tile_rows"] == (64 if rows else 34)
+        out[rows] = (vals, [g[0] for g in grads])
+    for i in range(len(Qs)):
+        assert rel(out[64][0][i], out[0][0][i]) < 1e-6 and rel(out[64][1][i], out[0][1][i]) < 1e-5, i
+
+
 def test_batched_falls_back_for_mixed_operator_kinds(ctx):
     say("batched call with a lattice field and a CSR field (per-field path)")
     f = dict(shape=(30, 20), kappa2=0.3)
