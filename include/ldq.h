@@ -139,7 +139,9 @@ enum {
   LDQ_COLOUR_MODULAR = 1,  /* (x + a y [+ b z]) mod C, smallest valid C (lattices only) */
   LDQ_COLOUR_GREEDY = 2,   /* sequential greedy in priority order (bit-exact on the device) */
   LDQ_COLOUR_USER = 3,     /* user_colours[n] */
-  LDQ_COLOUR_IDENTITY = 4  /* every site its own class (n probes; exact up to quadrature) */
+  LDQ_COLOUR_IDENTITY = 4, /* every site its own class (n probes; exact up to quadrature) */
+  LDQ_COLOUR_RADEMACHER = 5 /* no colouring: nrandom random-sign probes (Hutchinson's estimator,
+                               Sec. 2.1, eq. (6)); lattice operators only */
 };
 
 typedef struct {
@@ -170,6 +172,12 @@ typedef struct {
                                    others' streaming); 0 = chosen by the autotuner on 2-D lattices
                                    (1, 2 or 3, timed with the tile heights), 1 elsewhere.  Results
                                    are identical. */
+  int nrandom;                  /* LDQ_COLOUR_RADEMACHER: number s of probes; entry i of probe j is
+                                   +1 or -1 by the top bit of output j * 2^32 + i + 1 of the SplitMix64
+                                   generator (Steele, Lea and Flood 2014) started from `seed` (sites
+                                   numbered x + nx (y + ny z)); the result is the mean over probes,
+                                   (1/s) sum_j v_j^T log(Q) v_j, and likewise the gradient */
+  uint64_t seed;                /* LDQ_COLOUR_RADEMACHER: generator state */
 } ldq_options;
 
 /* launch_mode: AUTO and GRAPH capture one chunk of Krylov pass launches into a HIP graph (on a
@@ -204,6 +212,9 @@ typedef struct {
   int32_t lanes;             /* lattices: concurrent chains the passes ran in (a pass is then one
                                 launch per lane, over that lane's probes); 1 otherwise */
   int32_t tile_rows;         /* 2-D lattices: lattice rows per wave tile used; 0 otherwise */
+  double std_error;          /* LDQ_COLOUR_RADEMACHER: Monte Carlo standard error of the log det
+                                estimate (sample standard deviation of the per-probe terms over
+                                sqrt(s)); 0 for colourings (the probing estimate is deterministic) */
 } ldq_info;
 
 /* ------------------------------------------------------------- the method */

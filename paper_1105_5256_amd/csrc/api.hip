@@ -652,6 +652,8 @@ struct Colouring {
   int C = 0, a = 0, b = 0;          // modular parameters when C > 0 and colours == nullptr
   const int32_t *colours = nullptr; // device array otherwise
   int ncolours = 0;                 // C
+  bool rad = false;                 // random-sign probes 0 .. ncolours - 1 instead (no classes)
+  uint64_t seed = 0;
 };
 
 // Smallest C (then smallest coefficients) with x + a y [+ b z] != 0 mod C for
@@ -788,6 +790,7 @@ static int resolve_colouring(ldq_ctx *c, const ldq_op *Q, int k, int method, con
                              const int32_t *prio, Colouring *col) {
   const int64_t n = Q->n;
   if (method == LDQ_COLOUR_AUTO) method = (Q->kind == OPK_LATTICE) ? LDQ_COLOUR_MODULAR : LDQ_COLOUR_GREEDY;
+  if (method == LDQ_COLOUR_RADEMACHER) return LDQ_OK;   // set up by prepare_call
   if (method == LDQ_COLOUR_IDENTITY) {
     if (Q->kind == OPK_LATTICE && n < ((int64_t)1 << 31)) {
       // (x + nx y + nx ny z) mod n is the site index itself
@@ -1170,6 +1173,8 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     a3.cola = k.col.a;
     a3.colb = k.col.b;
     a3.colours = k.col.colours;
+    a3.rad = k.col.rad;
+    a3.seed = k.col.seed;
     a3.kappa2 = Q->kappa2;
     a3.kappa2_field = kfield;
     a3.scale = Q->scale;
@@ -1184,6 +1189,8 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     a2.colC = k.col.colours ? 0 : k.col.C;
     a2.cola = k.col.a;
     a2.colours = k.col.colours;
+    a2.rad = k.col.rad;
+    a2.seed = k.col.seed;
     a2.kappa2 = Q->kappa2;
     a2.kappa2_field = kfield;
     a2.scale = Q->scale;
@@ -1197,7 +1204,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   // the specialised 2-D pass: modular colouring, constant kappa2, gradient 0 a
   // shifted Laplacian with a constant shift, gradient 1 (with observations)
   // the observation gram of Q's own observations
-  bool fast2d = !is3d && !k.col.colours && !kfield && Q->scale == 1.0 &&
+  bool fast2d = !is3d && !k.col.colours && !k.col.rad && !kfield && Q->scale == 1.0 &&
                 (double)Q->n * sizeof(T) * (has_obs ? 9.0 : 1.0) < 4294967295.0;
   if (P >= 1) fast2d = fast2d && grads[0].kind == GK_SHIFTED && !grads[0].field;
   if (P >= 2)
@@ -1206,7 +1213,8 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   if (P >= 2 && fast2d) a2.grad[1].scale = k.dQ[1]->tau;
   // the specialised 3-D pass: modular colouring, scale 1, at most two diagonal
   // derivative operators, 32-bit byte offsets
-  bool fast3d = is3d && !k.col.colours && Q->scale == 1.0 && P <= 2 && (double)Q->n * sizeof(T) < 4294967295.0;
+  bool fast3d = is3d && !k.col.colours && !k.col.rad && Q->scale == 1.0 && P <= 2 &&
+                (double)Q->n * sizeof(T) < 4294967295.0;
   for (int i = 0; i < P; ++i) fast3d = fast3d && grads[i].kind == GK_DIAG;
   // Launch over probes p0 .. p0 + nprobes - 1 of the block with the probe state
   // and partials read from buffer `in` and written to 1 - in, on stream ls (the
@@ -1754,6 +1762,11 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
   if (!(k.o.tol > 0.0) || !(k.o.grad_tol >= 0.0) || k.o.max_iter < 1)
     return fail(LDQ_E_INVALID, "tol must be > 0, grad_tol >= 0, max_iter >= 1");
   if (k.o.precision != LDQ_FP64 && k.o.precision != LDQ_MIXED) return fail(LDQ_E_INVALID, "unknown precision");
+  if (k.o.colouring == LDQ_COLOUR_RADEMACHER) {
+    if (k.o.nrandom < 1 || k.o.nrandom > (1 << 20)) return fail(LDQ_E_INVALID, "nrandom must be in 1..2^20");
+    if (Q->kind != OPK_LATTICE)
+      return fail(LDQ_E_UNSUPPORTED, "random-sign probes are implemented for lattice operators");
+  }
   if (k.o.lanes < 0 || k.o.lanes > LDQ_MAX_LANES)
     return fail(LDQ_E_INVALID, "lanes must be in 0..%d", LDQ_MAX_LANES);
   if (Q->kind != OPK_LATTICE && Q->kind != OPK_CSR)
@@ -1778,7 +1791,14 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
   // are kept on the operator)
   CHK(resolve_colouring(c, Q, k.o.k, k.o.colouring, k.o.user_colours, k.o.priority, &k.col));
   const bool modular = !k.col.colours;
-  if (modular && Q->cls_C == k.col.C && Q->cls_a == k.col.a && Q->cls_b == k.col.b && !Q->cls.empty()) {
+  if (k.o.colouring == LDQ_COLOUR_RADEMACHER) {
+    // Hutchinson's estimator: probes 0 .. s - 1, every one over all sites
+    k.col.rad = true;
+    k.col.seed = k.o.seed;
+    k.col.ncolours = k.o.nrandom;
+    k.classes.resize(k.o.nrandom);
+    for (int j = 0; j < k.o.nrandom; ++j) k.classes[j] = j;
+  } else if (modular && Q->cls_C == k.col.C && Q->cls_a == k.col.a && Q->cls_b == k.col.b && !Q->cls.empty()) {
     k.classes = Q->cls;
   } else {
     const int C = k.col.ncolours;
@@ -1843,7 +1863,8 @@ static int tune_rows(Call &k) {
   char key[256];
   std::snprintf(key, sizeof key, "%lld,%lld,%d,%d,%d,%d,%d,%d,%d,%d,%d", (long long)Q->shape[0],
                 (long long)Q->shape[1], Q->lkind, k.o.precision, k.nparams, Q->obs9 != nullptr,
-                k.col.colours != nullptr, Q->field != nullptr, (int)k.classes.size(), k.o.probe_block, k.o.lanes);
+                (k.col.colours != nullptr) + 2 * k.col.rad, Q->field != nullptr, (int)k.classes.size(),
+                k.o.probe_block, k.o.lanes);
   auto it = k.c->tuned_rows.find(key);
   if (it != k.c->tuned_rows.end()) {
     k.rows2d = it->second % 1000;
@@ -1910,6 +1931,20 @@ static int logdet_impl(ldq_ctx *c, const ldq_op *Q, int nparams, const ldq_op *c
     st = (k.o.precision == LDQ_MIXED) ? run_krylov<float>(k, &tmp, sums) : run_krylov<double>(k, &tmp, sums);
   }
   if (st != LDQ_OK && st != LDQ_E_NO_CONVERGENCE) return st;
+  if (k.col.rad) {
+    // Hutchinson's estimator: the mean over the s probes, and the standard
+    // error of that mean from the per-probe terms
+    const int s = (int)k.classes.size();
+    for (int i = 0; i <= nparams; ++i) sums[i] /= s;
+    double m = 0.0, ss = 0.0;
+    for (int j = 0; j < s; ++j) m += c->last_terms[(size_t)j * (1 + nparams)];
+    m /= s;
+    for (int j = 0; j < s; ++j) {
+      const double d = c->last_terms[(size_t)j * (1 + nparams)] - m;
+      ss += d * d;
+    }
+    tmp.std_error = s > 1 ? std::sqrt(ss / (s - 1) / s) : INFINITY;
+  }
   if (logdet) *logdet = sums[0];
   if (grad)
     for (int i = 0; i < nparams; ++i) grad[i] = sums[1 + i];
@@ -1954,7 +1989,7 @@ static bool batchable(const std::vector<Call> &calls) {
     const ldq_op *Q = k.Q;
     if (Q->kind != OPK_LATTICE || Q->ndim != 2 || Q->field || Q->obs9 || Q->scale != 1.0) return false;
     if (Q->lkind != k0.Q->lkind) return false;
-    if (k.col.colours || k.col.C != k0.col.C || k.col.a != k0.col.a) return false;
+    if (k.col.colours || k.col.rad || k.col.C != k0.col.C || k.col.a != k0.col.a) return false;
     if (k.nparams != k0.nparams) return false;
     if (k.nparams == 1) {
       const ldq_op *d = k.dQ[0];

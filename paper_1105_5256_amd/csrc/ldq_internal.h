@@ -99,15 +99,31 @@ struct TailArgs {
 enum PassMode { MODE_INIT = 0, MODE_FIRST = 1, MODE_STEP = 2 };
 
 // 2-D lattice pass.
+// Entry `site` of random-sign probe j (Sec. 2.1, eq. (6): +1 or -1 with
+// probability 1/2, independently): the sign of the top bit of output number
+// j * 2^32 + site + 1 of the SplitMix64 generator started from `seed`
+// (Steele, Lea and Flood, OOPSLA 2014): z = seed + count * 0x9E3779B97F4A7C15,
+// then the generator's output mix of z.  Clear bit: +1.
+__host__ __device__ inline double rad_sign(uint64_t seed, int j, int64_t site) {
+  uint64_t z = seed + (((uint64_t)(uint32_t)j << 32) + (uint64_t)site + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (z >> 63) ? -1.0 : 1.0;
+}
+
 template <typename T>
 struct Pass2D {
   int nx, ny;
   int tiles_x, ntiles;
   int rows;                 // lattice rows per wave tile
   int nprobes;
-  // colouring: modular (C > 0) or array
+  // colouring: modular (C > 0) or array; or random signs (rad: probe j has
+  // entry rad_sign(seed, j, site) at every site)
   int colC, cola;
   const int32_t *colours;
+  int rad;
+  uint64_t seed;
   // operator
   double kappa2;            // constant shift (SQUARED and unfielded SHIFTED)
   const T *kappa2_field;    // SHIFTED with a field
@@ -130,6 +146,8 @@ struct Pass3D {
   int nprobes;
   int colC, cola, colb;
   const int32_t *colours;
+  int rad;                  // random-sign probes (as in Pass2D)
+  uint64_t seed;
   double kappa2;
   const T *kappa2_field;
   double scale;

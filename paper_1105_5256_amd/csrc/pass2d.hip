@@ -120,13 +120,16 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
     v += astep;
     return v >= C ? v - C : v;
   };
-  auto mine_at = [&](int y, int ay) -> bool {
+  // entry of the probe vector at (x, y) of this lane: 0 / 1 for a colour
+  // class, -1 / +1 for random signs (0 outside the lattice)
+  auto mine_at = [&](int y, int ay) -> double {
+    if (a.rad) return (xin && y >= 0 && y < ny) ? rad_sign(a.seed, colour, (int64_t)y * nx + x) : 0.0;
     if (C > 0) {
       int v = cx + ay;
       v -= (v >= C) ? C : 0;
-      return v == colour;
+      return v == colour ? 1.0 : 0.0;
     }
-    return xin && y >= 0 && y < ny && a.colours[(size_t)y * nx + xc] == colour;
+    return (xin && y >= 0 && y < ny && a.colours[(size_t)y * nx + xc] == colour) ? 1.0 : 0.0;
   };
   int ay_in = row_part(ylo);                       // row part of the arriving row
   int ay_g = row_part(ylo - 1);                    // ... of the gradient row y - 1
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
       // ---- row y arrives: p_k = r_k + beta p_{k-1}, rounded to the storage precision
       T r_y, p_y;
       if constexpr (GEN) {
-        r_y = (yin && mine_at(y, ay_in)) ? T(1) : T(0);
+        r_y = yin ? (T)mine_at(y, ay_in) : T(0);
         p_y = r_y;
       } else {
         r_y = xin ? qr[u] : T(0);
@@ -235,24 +238,24 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
       if constexpr (NG > 0) {
         const int yg = y - 1;
         const int ug = (u + 4) % 5;
-        const bool gout = xout && yg >= y0 && yg < yb && mine_at(yg, ay_g);
+        const double gw = (xout && yg >= y0 && yg < yb) ? mine_at(yg, ay_g) : 0.0;
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
           const GradTerm<T> &gt = a.grad[g];
           if (gt.kind == GK_SHIFTED) {
             const double kd = gt.field ? (yin ? (double)gt.field[(size_t)y * nx + xc] : 0.0) : gt.kappa2;
             macc[g][ug] -= p;                                       // row y - 1 complete
-            q[LDQ_NQ_BASE + g] += gout ? gt.scale * macc[g][ug] : 0.0;
+            q[LDQ_NQ_BASE + g] += gw * gt.scale * macc[g][ug];
             macc[g][u] += (kd + 4.0) * p - h1;
             macc[g][(u + 1) % 5] = -p;
           } else if (gt.kind == GK_DIAG) {
-            if (gout) q[LDQ_NQ_BASE + g] += gt.scale * (double)gt.field[(size_t)yg * nx + xc] * (double)pq[ug];
+            if (gw != 0.0) q[LDQ_NQ_BASE + g] += gw * gt.scale * (double)gt.field[(size_t)yg * nx + xc] * (double)pq[ug];
           } else if constexpr (OBS) {
             // GK_OBS (the host allows it only when Q has an observation term)
-            if (gout) {
+            if (gw != 0.0) {
               const int um = (u + 3) % 5;
-              q[LDQ_NQ_BASE + g] += gt.scale * obs_apply(gt.obs, n, (size_t)yg * nx + xc, pl[um], pq[um], pr[um],
-                                                         pl[ug], pq[ug], pr[ug], pl[u], pq[u], pr[u]);
+              q[LDQ_NQ_BASE + g] += gw * gt.scale * obs_apply(gt.obs, n, (size_t)yg * nx + xc, pl[um], pq[um], pr[um],
+                                                              pl[ug], pq[ug], pr[ug], pl[u], pq[u], pr[u]);
             }
           }
         }
@@ -304,7 +307,7 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
         if constexpr (OBS) qv += r2 * obs_r[ud];
         q[0] += r2 * r2;
         q[1] += qv;
-        q[2] += (dout && mine_at(yd, ay_d)) ? r2 : 0.0;
+        q[2] += dout ? mine_at(yd, ay_d) * r2 : 0.0;
       }
       ay_d = advance(ay_d);
     }

@@ -24,6 +24,13 @@ __device__ inline int colour3(const Pass3D<T> &a, int x, int y, int z) {
   return a.colC > 0 ? (x + a.cola * y + a.colb * z) % a.colC
                     : a.colours[((size_t)z * a.ny + y) * a.nx + x];
 }
+// Entry of probe `colour` at a site inside the lattice: 0 / 1 for a colour
+// class, -1 / +1 for random signs.
+template <typename T>
+__device__ inline double probe3(const Pass3D<T> &a, int colour, int x, int y, int z) {
+  if (a.rad) return rad_sign(a.seed, colour, ((int64_t)z * a.ny + y) * a.nx + x);
+  return colour3(a, x, y, z) == colour ? 1.0 : 0.0;
+}
 
 template <typename T>
 __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
@@ -73,7 +80,7 @@ __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
         const double qr = a.scale * (k2at(s) * r + lap);
         q[0] += r * r;
         q[1] += r * qr;
-        if (colour3(a, gx, gy, z) == colour) q[2] += r;
+        q[2] += probe3(a, colour, gx, gy, z) * r;
       }
     }
   };
@@ -85,7 +92,7 @@ __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
       for (int e = tid; e < RW * RH; e += LDQ_BLOCK) {
         const int ry = e / RW, rx = e - ry * RW;
         const int gx = x0 - 1 + rx, gy = y0 - 1 + ry;
-        dst[ry][rx] = (inbox(gx, gy, t) && colour3(a, gx, gy, t) == colour) ? T(1) : T(0);
+        dst[ry][rx] = inbox(gx, gy, t) ? (T)probe3(a, colour, gx, gy, t) : T(0);
       }
       __syncthreads();
       if (t - 1 >= z0) dots_plane(t - 1);
@@ -101,7 +108,7 @@ __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
         if (inbox(gx, gy, z)) {
           const size_t s = site(gx, gy, z);
           if (a.mode == MODE_FIRST) {
-            r = (colour3(a, gx, gy, z) == colour) ? T(1) : T(0);
+            r = (T)probe3(a, colour, gx, gy, z);
             p = r;
           } else {
             r = a.r_in[off + s];
@@ -141,7 +148,8 @@ __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
             if (own && rx >= 1 && rx <= T3X && ry >= 1 && ry <= T3Y) {
               a.r_out[off + s] = rn;
               a.p_out[off + s] = pc[py][px];
-              if (colour3(a, gx, gy, t) == colour) {
+              const double vw = probe3(a, colour, gx, gy, t);
+              if (vw != 0.0) {
 #pragma unroll
                 for (int i = 0; i < LDQ_MAXP; ++i) {
                   if (i >= a.tail.ngrad) break;
@@ -153,7 +161,7 @@ __global__ __launch_bounds__(LDQ_BLOCK) void pass3d_kernel(Pass3D<T> a) {
                     const double k2 = g.field ? (double)g.field[s] : g.kappa2;
                     d = k2 * pv + 6.0 * pv - nb;
                   }
-                  q[LDQ_NQ_BASE + i] += g.scale * d;
+                  q[LDQ_NQ_BASE + i] += vw * g.scale * d;
                 }
               }
             }

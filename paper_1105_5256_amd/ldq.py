@@ -22,6 +22,7 @@ LDQ_SHIFTED_LAPLACIAN, LDQ_SQUARED_SHIFTED_LAPLACIAN = 1, 2
 LDQ_FLAG_DEVICE_PTR = 1
 LDQ_FP64, LDQ_MIXED = 0, 1
 LDQ_COLOUR_AUTO, LDQ_COLOUR_MODULAR, LDQ_COLOUR_GREEDY, LDQ_COLOUR_USER, LDQ_COLOUR_IDENTITY = 0, 1, 2, 3, 4
+LDQ_COLOUR_RADEMACHER = 5
 LDQ_LAUNCH_AUTO, LDQ_LAUNCH_GRAPH, LDQ_LAUNCH_DIRECT = 0, 1, 2
 
 
@@ -43,6 +44,8 @@ class ldq_options(ctypes.Structure):
         ("launch_mode", ctypes.c_int),
         ("tile_rows", ctypes.c_int),
         ("lanes", ctypes.c_int),
+        ("nrandom", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
     ]
 
 
@@ -62,6 +65,7 @@ class ldq_info(ctypes.Structure):
         ("enclosure_violations", ctypes.c_int32),
         ("lanes", ctypes.c_int32),
         ("tile_rows", ctypes.c_int32),
+        ("std_error", ctypes.c_double),
     ]
 
     def as_dict(self):

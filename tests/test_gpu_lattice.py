@@ -269,8 +269,10 @@ def test_two_lanes_agree(ctx, shape, kind, k, precision, rows):
     for lanes, block, mode in ((1, 0, ldq.LDQ_LAUNCH_AUTO), (2, 0, ldq.LDQ_LAUNCH_AUTO), (2, 0, ldq.LDQ_LAUNCH_DIRECT),
                                (1, 7, ldq.LDQ_LAUNCH_AUTO), (2, 7, ldq.LDQ_LAUNCH_GRAPH), (3, 0, ldq.LDQ_LAUNCH_AUTO),
                                (4, 7, ldq.LDQ_LAUNCH_DIRECT)):
+        # rows 0: the standard tile, fixed (left to the autotuner, calls with other lane
+        # settings may time another tile height best, which changes the order of the sums)
         opts = ldq.ldq_options_default(k=k, tol=1e-6, grad_tol=1e-7, precision=precision, probe_block=block,
-                                       check_every=6, launch_mode=mode, lanes=lanes, tile_rows=rows)
+                                       check_every=6, launch_mode=mode, lanes=lanes, tile_rows=rows or 32)
         v, g, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
         res.append((v, g[0], info["iters_total"], ldq.ldq_probe_terms(ctx.handle)))
     for i in (1, 2, 5):
@@ -290,12 +292,14 @@ def test_lanes_autotuned(ctx):
     dQ = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, 0.05, scale=2.0))
     out = {}
     for lanes in (0, 1, 2, 3):
-        opts = ldq.ldq_options_default(k=4, tol=1e-5, grad_tol=1e-5, precision=ldq.LDQ_MIXED, lanes=lanes)
+        # forced lanes on the standard tile; lanes 0 leaves lanes and tile to the autotuner
+        opts = ldq.ldq_options_default(k=4, tol=1e-5, grad_tol=1e-5, precision=ldq.LDQ_MIXED, lanes=lanes,
+                                       tile_rows=32 if lanes else 0)
         v, g, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
         out[lanes] = (v, g[0])
         assert info["lanes"] == (lanes if lanes else info["lanes"]) and 1 <= info["lanes"] <= 3
     assert out[2] == out[1] and out[3] == out[1]
-    assert rel(out[0][0], out[1][0]) < 1e-12 and rel(out[0][1], out[1][1]) < 1e-11
+    assert rel(out[0][0], out[1][0]) < 1e-6 and rel(out[0][1], out[1][1]) < 1e-5
 
 
 # the tall tile of the FP32 fast pass (64 rows: interior and boundary tiles,
