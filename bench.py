@@ -63,7 +63,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default per workload)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="lattice512_sq",
-                    choices=["lattice512_sq", "lattice64_5pt", "field128", "posterior1024", "batch256"])
+                    choices=["lattice512_sq", "lattice64_5pt", "field128", "posterior1024", "batch256",
+                             "hutch512"])
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--no-forms", action="store_true", help="skip the other forms and the accuracy runs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -98,6 +99,19 @@ class Workload:
             # form: the autotuner's choice here, fixed so that a run under the profiler (which slows
             # the tuner's short timing runs unevenly) makes the same choice
             self.pin = {L.LDQ_MIXED: dict(lanes=2, tile_rows=34)}
+        elif name == "hutch512":
+            # Hutchinson's estimator (random-sign probes, Sec. 2.1 eq. (6)) on the 512x512 operator:
+            # as many probes as the distance-4 colouring has classes
+            wl = workloads.lattice2d_sq(512, kappa2=0.05, k=4)
+            self.wl = wl
+            self.Q = ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SQUARED_SHIFTED_LAPLACIAN, wl["kappa2"]))
+            self.dQ = [ctx.op(L.ldq_op_lattice(h, wl["shape"], L.LDQ_SHIFTED_LAPLACIAN, wl["kappa2"], scale=2.0))]
+            self.timed, self.k, self.tol, self.gtol = L.LDQ_MIXED, 4, 1e-4, 1e-4
+            self.extra = dict(colouring=L.LDQ_COLOUR_RADEMACHER, nrandom=41, seed=0x5EED)
+            self.describe = ("hutch512: 2-D 512x512 lattice, Q = (0.05 I + L)^2 (13-point), Hutchinson's estimator "
+                             "with 41 random-sign probes (SplitMix64, seed 0x5EED), N=20 shifts, log det + d/dkappa2")
+            self.kernel = "pass2d_kernel<float, R=2, 1 gradient> (general 2-D pass, random-sign probes)"
+            self.n = 512 * 512
         elif name == "lattice64_5pt":
             wl = workloads.lattice2d_5pt(64, 0.1, 2)
             self.wl = wl
@@ -156,7 +170,7 @@ class Workload:
     def opts(self, precision, tol, gtol):
         from paper_1105_5256_amd import ldq
         return ldq.ldq_options_default(k=self.k, nshifts=20, tol=tol, grad_tol=gtol, precision=precision,
-                                       **getattr(self, "pin", {}).get(precision, {}))
+                                       **getattr(self, "pin", {}).get(precision, {}), **getattr(self, "extra", {}))
 
     def run(self, opts):
         """One evaluation: (values, gradients, list of info dicts)."""
@@ -295,7 +309,8 @@ def csr_forms(ctx, wl, nsteps, ref_val, ref_grad, tol, gtol):
     return res
 
 
-DEFAULT_STEPS = {"lattice512_sq": 10, "lattice64_5pt": 20, "field128": 3, "posterior1024": 3, "batch256": 2}
+DEFAULT_STEPS = {"lattice512_sq": 10, "lattice64_5pt": 20, "field128": 3, "posterior1024": 3, "batch256": 2,
+                 "hutch512": 3}
 
 
 def main():
@@ -365,6 +380,9 @@ def main():
                    "lanes": max(i["lanes"] for i in one_eval), "tile_rows": max(i["tile_rows"] for i in one_eval)},
         "roofline": roofline,
     }
+    if getattr(w, "extra", None):
+        # random-sign probes: the estimate's Monte Carlo standard error
+        out["config"]["std_error"] = one_eval[0]["std_error"]
 
     if not args.no_forms:
         # accuracy: the timed result against a tight FP64 run of the same library
