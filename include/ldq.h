@@ -141,7 +141,7 @@ enum {
   LDQ_COLOUR_USER = 3,     /* user_colours[n] */
   LDQ_COLOUR_IDENTITY = 4, /* every site its own class (n probes; exact up to quadrature) */
   LDQ_COLOUR_RADEMACHER = 5 /* no colouring: nrandom random-sign probes (Hutchinson's estimator,
-                               Sec. 2.1, eq. (6)); lattice operators only */
+                               Sec. 2.1, eq. (6)); lattice and CSR operators, single calls */
 };
 
 typedef struct {

@@ -1618,6 +1618,8 @@ static int run_krylov_csr(Call &k, ldq_info *info, double *out_sums) {
   a.val = sl->val.as<double>();
   for (int i = 0; i < P; ++i) a.gval[i] = sl->gval[i].as<double>();
   a.colours = k.col.colours;
+  a.rad = k.col.rad;
+  a.seed = k.col.seed;
   a.st = st;
   a.part = part;
 
@@ -1764,8 +1766,6 @@ static int prepare_call(Call &k, ldq_ctx *c, const ldq_op *Q, int nparams, const
   if (k.o.precision != LDQ_FP64 && k.o.precision != LDQ_MIXED) return fail(LDQ_E_INVALID, "unknown precision");
   if (k.o.colouring == LDQ_COLOUR_RADEMACHER) {
     if (k.o.nrandom < 1 || k.o.nrandom > (1 << 20)) return fail(LDQ_E_INVALID, "nrandom must be in 1..2^20");
-    if (Q->kind != OPK_LATTICE)
-      return fail(LDQ_E_UNSUPPORTED, "random-sign probes are implemented for lattice operators");
   }
   if (k.o.lanes < 0 || k.o.lanes > LDQ_MAX_LANES)
     return fail(LDQ_E_INVALID, "lanes must be in 0..%d", LDQ_MAX_LANES);

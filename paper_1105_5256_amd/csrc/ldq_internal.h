@@ -210,6 +210,8 @@ struct PassCsr {
   const double *val;            // operator values stay FP64 in both precisions
   const double *gval[LDQ_MAXP];
   const int32_t *colours;
+  int rad;                      // random-sign probes (rad_sign(seed, j, row)); colours unused
+  uint64_t seed;
   const ProbeState *st;
   const T *r_in, *p_in;
   T *r_out, *p_out;

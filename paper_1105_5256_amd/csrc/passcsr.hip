@@ -244,10 +244,15 @@ __global__ __launch_bounds__(256) void csr_pass_a_kernel(PassCsr<T> a) {
     load_slice<T, W, NG>(a, ws, R);
     if constexpr (FIRST) {
 #pragma unroll
-      for (int k = 0; k < W; ++k) ccol[k] = a.colours[R.off[k] / (uint32_t)sizeof(T)];
+      for (int k = 0; k < W; ++k) ccol[k] = a.rad ? 0 : a.colours[R.off[k] / (uint32_t)sizeof(T)];
     }
   }
-  const int mycol = a.colours[ws.row];
+  const int mycol = a.rad ? 0 : a.colours[ws.row];
+  // entry of probe j (colour cj) at a row: 0 / 1 for a colour class, -1 / +1
+  // for random signs
+  auto probe_at = [&](int cj, int64_t row, int colour_of_row) -> double {
+    return a.rad ? rad_sign(a.seed, cj, row) : (colour_of_row == cj ? 1.0 : 0.0);
+  };
   constexpr int NQ = 2 + NG;
   int slot[NQ];
   slot[0] = 0;   // gamma'
@@ -275,10 +280,11 @@ __global__ __launch_bounds__(256) void csr_pass_a_kernel(PassCsr<T> a) {
       if constexpr (FIRST) {
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-          if (ccol[k] == cj) {
-            q += R.val[k];
+          const double w = probe_at(cj, R.off[k] / (uint32_t)sizeof(T), ccol[k]);
+          if (w != 0.0) {
+            q = fma(R.val[k], w, q);
 #pragma unroll
-            for (int i = 0; i < NG; ++i) dq[i] += R.gv[i][k];
+            for (int i = 0; i < NG; ++i) dq[i] = fma(R.gv[i][k], w, dq[i]);
           }
         }
       } else {
@@ -304,7 +310,7 @@ __global__ __launch_bounds__(256) void csr_pass_a_kernel(PassCsr<T> a) {
         const int32_t c = a.col[e];
         double x;
         if constexpr (FIRST)
-          x = (a.colours[c] == cj) ? 1.0 : 0.0;
+          x = probe_at(cj, c, a.rad ? 0 : a.colours[c]);
         else
           x = fma(beta, (double)pb[c], (double)rb[c]);
         q = fma(a.val[e], x, q);
@@ -312,10 +318,11 @@ __global__ __launch_bounds__(256) void csr_pass_a_kernel(PassCsr<T> a) {
         for (int i = 0; i < NG; ++i) dq[i] = fma(a.gval[i][e], x, dq[i]);
       }
     }
-    const bool mine = ws.valid && mycol == cj;
+    const double vown = probe_at(cj, ws.row, mycol);
+    const double mine = ws.valid ? vown : 0.0;
     double rown, pown;
     if constexpr (FIRST) {
-      rown = (mycol == cj) ? 1.0 : 0.0;
+      rown = vown;
       pown = rown;
     } else {
       rown = (double)rb[ws.row];
@@ -328,9 +335,9 @@ __global__ __launch_bounds__(256) void csr_pass_a_kernel(PassCsr<T> a) {
     }
     double qs[NQ];
     qs[0] = ws.valid ? rnew * rnew : 0.0;
-    qs[1] = mine ? rnew : 0.0;
+    qs[1] = mine * rnew;
 #pragma unroll
-    for (int i = 0; i < NG; ++i) qs[2 + i] = mine ? dq[i] : 0.0;
+    for (int i = 0; i < NG; ++i) qs[2 + i] = mine * dq[i];
     put_partials<NQ>(a.part, a.nq, a.nslices, j, ws.s, slot, qs);
   }
   }
@@ -347,10 +354,13 @@ __global__ __launch_bounds__(256) void csr_pass_b_kernel(PassCsr<T> a) {
     load_slice<T, W, 0>(a, ws, R);
     if constexpr (INIT) {
 #pragma unroll
-      for (int k = 0; k < W; ++k) ccol[k] = a.colours[R.off[k] / (uint32_t)sizeof(T)];
+      for (int k = 0; k < W; ++k) ccol[k] = a.rad ? 0 : a.colours[R.off[k] / (uint32_t)sizeof(T)];
     }
   }
-  const int mycol = a.colours[ws.row];
+  const int mycol = a.rad ? 0 : a.colours[ws.row];
+  auto probe_at = [&](int cj, int64_t row, int colour_of_row) -> double {
+    return a.rad ? rad_sign(a.seed, cj, row) : (colour_of_row == cj ? 1.0 : 0.0);
+  };
   for (int c0 = 0; c0 < a.nprobes; c0 += 64) {
   const ProbeChunk pc = load_chunk(a.st, c0, a.nprobes);
   const int cnt = min(64, a.nprobes - c0);
@@ -364,8 +374,7 @@ __global__ __launch_bounds__(256) void csr_pass_b_kernel(PassCsr<T> a) {
     if constexpr (W > 0) {
       if constexpr (INIT) {
 #pragma unroll
-        for (int k = 0; k < W; ++k)
-          if (ccol[k] == cj) s += R.val[k];
+        for (int k = 0; k < W; ++k) s = fma(R.val[k], probe_at(cj, R.off[k] / (uint32_t)sizeof(T), ccol[k]), s);
       } else {
         const __amdgpu_buffer_rsrc_t rx = make_rsrc(xb, (unsigned)(n * (int64_t)sizeof(T)));
         T xv[W];
@@ -378,15 +387,15 @@ __global__ __launch_bounds__(256) void csr_pass_b_kernel(PassCsr<T> a) {
       for (int k = 0; k < ws.w; ++k) {
         const int64_t e = ws.off + (int64_t)k * 64 + ws.lane;
         const int32_t c = a.col[e];
-        const double x = INIT ? ((a.colours[c] == cj) ? 1.0 : 0.0) : (double)xb[c];
+        const double x = INIT ? probe_at(cj, c, a.rad ? 0 : a.colours[c]) : (double)xb[c];
         s = fma(a.val[e], x, s);
       }
     }
-    const double xo = INIT ? ((mycol == cj) ? 1.0 : 0.0) : (double)xb[ws.row];
+    const double xo = INIT ? probe_at(cj, ws.row, mycol) : (double)xb[ws.row];
     if constexpr (INIT) {
       // dots of r_0 = v: |v|^2, v^T Q v, v^T v
       const int slot[3] = {0, 1, 2};
-      double qs[3] = {ws.valid ? xo : 0.0, ws.valid ? xo * s : 0.0, ws.valid ? xo : 0.0};
+      double qs[3] = {ws.valid ? xo * xo : 0.0, ws.valid ? xo * s : 0.0, ws.valid ? xo * xo : 0.0};
       put_partials<3>(a.part, a.nq, a.nslices, j, ws.s, slot, qs);
     } else {
       const int slot[1] = {1};

@@ -13,7 +13,7 @@ import pytest
 import scipy.sparse as sp
 
 from oracle import exact, hutchinson as hu, lattice, shifts
-from paper_1105_5256_amd import ldq
+from paper_1105_5256_amd import ldq, workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -91,15 +91,37 @@ def test_hutchinson_seed_changes_probes_and_estimate_covers_exact(ctx):
     assert len(set(vals)) == 3
 
 
+# general sparse operators: the CSR passes draw the same signs per row
+@pytest.mark.parametrize("n,wide,precision,bound", [(700, False, ldq.LDQ_FP64, 1e-8),
+                                                    (900, True, ldq.LDQ_FP64, 1e-8),
+                                                    (700, False, ldq.LDQ_MIXED, 1e-4)])
+def test_hutchinson_csr_matches_oracle(ctx, n, wide, precision, bound):
+    s, seed = 10, 77
+    say(f"hutchinson CSR n={n} wide={wide} precision={precision}")
+    rp, ci, v = workloads.random_spd_csr(n, 20 if wide else 2, 60 if wide else 8, shift=0.05, seed=n)
+    Q = ctx.op(ldq.ldq_op_csr(ctx.handle, n, rp, ci, v))
+    Qm = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    d = np.linspace(0.5, 2.0, n)
+    D = ctx.op(ldq.ldq_op_diag(ctx.handle, d))
+    val, g, info = ldq.ldq_logdet_grad(ctx.handle, Q, [D], hopts(s, seed, tol=1e-10 if precision == ldq.LDQ_FP64
+                                                                    else 1e-5, grad_tol=1e-10 if precision ==
+                                                                    ldq.LDQ_FP64 else 1e-5, precision=precision))
+    terms = ldq.ldq_probe_terms(ctx.handle)
+    V = hu.rademacher(n, s, seed)
+    sig, coef = shifts.log_shifts(info["lambda_min"], info["lambda_max"], 20)
+    H, T = hu.hutchinson_rational(Qm, V, sig, coef)
+    G, _ = hu.hutchinson_grad(Qm, [sp.diags(d)], V)
+    print(f"logdet rel {rel(val, H):.1e}, grad rel {rel(g[0], G[0]):.1e}, max term rel "
+          f"{np.max(np.abs(terms[:, 0] - T) / np.abs(T)):.1e}, iters {info['iters_max']}")
+    assert np.allclose(terms[:, 0], T, rtol=bound, atol=0)
+    assert rel(val, H) < bound and rel(g[0], G[0]) < 10 * bound
+    assert rel(info["std_error"], hu.standard_error(T)) < (1e-3 if precision == ldq.LDQ_MIXED else 1e-6)
+
+
 def test_hutchinson_error_paths(ctx):
     say("hutchinson error paths")
     Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, (20, 20), ldq.LDQ_SHIFTED_LAPLACIAN, 0.3))
-    with pytest.raises(ldq.LdqError) as e:
-        ldq.ldq_logdet(ctx.handle, Q, hopts(0, 1))
-    assert e.value.status == ldq.LDQ_E_INVALID
-    rp = np.arange(5, dtype=np.int32)
-    ci = np.arange(4, dtype=np.int32)
-    C = ctx.op(ldq.ldq_op_csr(ctx.handle, 4, rp, ci, np.full(4, 2.0)))
-    with pytest.raises(ldq.LdqError) as e:
-        ldq.ldq_logdet(ctx.handle, C, hopts(4, 1))
-    assert e.value.status == ldq.LDQ_E_UNSUPPORTED
+    for s in (0, -3):
+        with pytest.raises(ldq.LdqError) as e:
+            ldq.ldq_logdet(ctx.handle, Q, hopts(s, 1))
+        assert e.value.status == ldq.LDQ_E_INVALID
