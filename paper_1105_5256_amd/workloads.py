@@ -24,7 +24,10 @@ are synthetic stand-ins with the same operators and scales:
                       "CSR form" of the 512 x 512 workload);
 * ``random_spd_csr``  a seeded sparse SPD matrix on a random graph of uneven
                       degree (weighted graph Laplacian plus a positive
-                      diagonal), for the general sparse path.
+                      diagonal), for the general sparse path;
+* ``spde_field_sample`` an exact draw of the directly observed field of
+                      Q = tau^2 (kappa2 I + L)^2 (the data of the
+                      hyperparameter fit).
 """
 import numpy as np
 
@@ -38,6 +41,22 @@ def lattice2d_sq(mx=512, my=None, kappa2=0.05, k=4):
     """Squared operator (kappa2 I + L)^2 on an mx x my lattice."""
     my = mx if my is None else my
     return dict(kind="sq", shape=(mx, my), kappa2=float(kappa2), power=2, k=int(k))
+
+
+def spde_field_sample(shape, kappa2, tau, seed):
+    """A draw x ~ N(0, Q^{-1}) of the directly observed 2-D SPDE field with
+    Q = tau^2 (kappa2 I + L)^2 (L the 5-point Dirichlet Laplacian): L is
+    diagonalised by the orthonormal DST-I, with eigenvalue
+    4 sin^2(pi i / (2 (mx + 1))) + 4 sin^2(pi j / (2 (my + 1))) at frequency
+    (i, j), so x = S (w / (tau (kappa2 + lambda))) with w ~ N(0, I).
+    Returned flat in site order (x fastest)."""
+    import scipy.fft as sfft
+    mx, my = (int(m) for m in shape)
+    lx = 4.0 * np.sin(np.pi * np.arange(1, mx + 1) / (2.0 * (mx + 1))) ** 2
+    ly = 4.0 * np.sin(np.pi * np.arange(1, my + 1) / (2.0 * (my + 1))) ** 2
+    lam = ly[:, None] + lx[None, :]                     # array shape (my, mx)
+    w = np.random.default_rng(seed).standard_normal((my, mx))
+    return sfft.idstn(w / (tau * (kappa2 + lam)), type=1, norm="ortho").ravel()
 
 
 def smooth_field(shape, sigma, seed):

@@ -40,3 +40,14 @@ def test_random_spd_csr_is_symmetric_positive_definite():
     ea = np.linalg.eigvalsh(sp.csr_matrix((a[2], a[1], a[0]), shape=(300, 300)).toarray())
     eb = np.linalg.eigvalsh(sp.csr_matrix((b[2], b[1], b[0]), shape=(300, 300)).toarray())
     assert np.allclose(ea, eb, rtol=1e-12, atol=1e-12)
+
+
+def test_spde_field_sample_has_covariance_q_inverse():
+    # x^T Q x of an exact draw from N(0, Q^{-1}) is chi-square with n degrees of freedom
+    from oracle import lattice
+    shape, k2, tau = (20, 17), 0.5, 2.0
+    n = shape[0] * shape[1]
+    Q = (tau * tau * lattice.squared(lattice.shifted_laplacian(shape, k2))).tocsr()
+    vals = np.array([float(x @ (Q @ x)) for x in (workloads.spde_field_sample(shape, k2, tau, s) for s in range(300))])
+    assert abs(vals.mean() - n) < 5 * np.sqrt(2 * n / len(vals))
+    assert abs(vals.std() / np.sqrt(2 * n) - 1) < 0.25
