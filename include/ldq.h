@@ -257,6 +257,21 @@ int ldq_logdet_grad(ldq_ctx *ctx, const ldq_op *Q, int nparams, const ldq_op *co
  * order.  capacity = length of out; *count receives the number of probes. */
 int ldq_probe_terms(ldq_ctx *ctx, double *out, int64_t capacity, int64_t *count, int *nparams);
 
+/* Y = f_N(Q) V: the rational approximation of eq. (7) (Sec. 2.1) of log(Q)
+ * applied to nvec vectors, Im sum_l c_l (Q - sigma_l I)^{-1} v_j, with the
+ * enclosure, shifts and tolerances of opts (colouring fields ignored).
+ * V and Y are DEVICE arrays of nvec x n doubles, vector j at [j * n]
+ * (owned by the caller; Y is overwritten).  The shifted solutions are not
+ * stored: a first Krylov solve records the base CG coefficients, the host
+ * forms per-iteration weights w_m = Im sum_l c_l zeta^l_m S^l_m of the
+ * residuals (x^l = sum_m zeta^l_m S^l_m r_m), and a second, identical solve
+ * accumulates Y = sum_m w_m r_m (two solves and one extra vector per probe).
+ * Lattice operators; at most 8192 iterations per vector (LDQ_E_UNSUPPORTED
+ * beyond).  info describes the first solve.  v_j^T y_j is the probe term of
+ * the log det estimate for probe v_j. */
+int ldq_logm_apply(ldq_ctx *ctx, const ldq_op *Q, int nvec, const double *V, double *Y, const ldq_options *opts,
+                   ldq_info *info /* nullable */);
+
 /* Many independent fields (e.g. one operator per field); per field f:
  * logdet[f], grad[f * nparams + i] (dQ[f * nparams + i]), info[f] (nullable). */
 int ldq_logdet_batched(ldq_ctx *ctx, int nfields, const ldq_op *const *Q, int nparams,

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <array>
+#include <complex>
 #include <map>
 #include <mutex>
 #include <string>
@@ -58,6 +59,9 @@ hipError_t launch_lanczos_check(const double *, const ProbeState *, int, int, do
 hipError_t launch_batch_lanczos_check(const double *, const ProbeState *, int, int, const int32_t *, const double *,
                                       int *, hipStream_t);
 template <typename T> hipError_t launch_batch2d(const Batch2D<T> &, int, bool, int, hipStream_t);
+template <typename S>
+hipError_t launch_mat_accum(const S *x, const double *w, int wstride, int m, int nb, int64_t n, double *y, bool init,
+                            hipStream_t s);
 hipError_t launch_batch_compact(const FieldDesc *, const int32_t *, int, const ProbeState *, ProbeState *, WorkItem *,
                                 int *, hipStream_t);
 }  // namespace ldq
@@ -142,6 +146,7 @@ struct ldq_ctx {
   hipStream_t stream = nullptr;
   DevBuf vec, partials, pstate, sstate, shifts, classes, terms, stats, sums, misc, colbuf, jpkey, jpmask, hist;
   DevBuf bfields, bitems, bwork, blohi;   // batched lattice passes
+  DevBuf matw;                            // weights of a materialisation of f_N(Q) v
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evp[2] = {nullptr, nullptr};   // convergence polls
   int *hpin = nullptr;                      // pinned host copies of the device counters
@@ -246,7 +251,7 @@ extern "C" void ldq_destroy(ldq_ctx *c) {
   hipStreamSynchronize(c->stream);
   for (DevBuf *b : {&c->vec, &c->partials, &c->pstate, &c->sstate, &c->shifts, &c->classes,
                     &c->terms, &c->stats, &c->sums, &c->misc, &c->colbuf, &c->jpkey, &c->jpmask, &c->hist,
-                    &c->bfields, &c->bitems, &c->bwork, &c->blohi})
+                    &c->bfields, &c->bitems, &c->bwork, &c->blohi, &c->matw})
     b->release();
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
@@ -654,6 +659,7 @@ struct Colouring {
   int ncolours = 0;                 // C
   bool rad = false;                 // random-sign probes 0 .. ncolours - 1 instead (no classes)
   uint64_t seed = 0;
+  const double *uvec = nullptr;     // or given probe vectors 0 .. ncolours - 1 (device, [probe][n])
 };
 
 // Smallest C (then smallest coefficients) with x + a y [+ b z] != 0 mod C for
@@ -876,6 +882,11 @@ struct Call {
   int stats[8];
   int rows2d;        // 2-D lattices: rows per wave tile (0: the specialised pass's standard tile)
   int lanes;         // lattices: concurrent chains of pass launches per probe block (1..LDQ_MAX_LANES)
+  // materialising f_N(Q) v (second solve): y_j = sum_m w[j][m] r_m of probe j,
+  // accumulated over `mat_steps` iterations (lattice operators, one block)
+  const double *mat_w;
+  int mat_wstride, mat_steps;
+  double *mat_y;
   double *tune_ms;   // non-null: a timing run of the autotuner (a few passes of the first probe block)
 };
 
@@ -1175,6 +1186,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     a3.colours = k.col.colours;
     a3.rad = k.col.rad;
     a3.seed = k.col.seed;
+    a3.uvec = k.col.uvec;
     a3.kappa2 = Q->kappa2;
     a3.kappa2_field = kfield;
     a3.scale = Q->scale;
@@ -1191,6 +1203,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     a2.colours = k.col.colours;
     a2.rad = k.col.rad;
     a2.seed = k.col.seed;
+    a2.uvec = k.col.uvec;
     a2.kappa2 = Q->kappa2;
     a2.kappa2_field = kfield;
     a2.scale = Q->scale;
@@ -1204,7 +1217,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   // the specialised 2-D pass: modular colouring, constant kappa2, gradient 0 a
   // shifted Laplacian with a constant shift, gradient 1 (with observations)
   // the observation gram of Q's own observations
-  bool fast2d = !is3d && !k.col.colours && !k.col.rad && !kfield && Q->scale == 1.0 &&
+  bool fast2d = !is3d && !k.col.colours && !k.col.rad && !k.col.uvec && !kfield && Q->scale == 1.0 &&
                 (double)Q->n * sizeof(T) * (has_obs ? 9.0 : 1.0) < 4294967295.0;
   if (P >= 1) fast2d = fast2d && grads[0].kind == GK_SHIFTED && !grads[0].field;
   if (P >= 2)
@@ -1213,7 +1226,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   if (P >= 2 && fast2d) a2.grad[1].scale = k.dQ[1]->tau;
   // the specialised 3-D pass: modular colouring, scale 1, at most two diagonal
   // derivative operators, 32-bit byte offsets
-  bool fast3d = is3d && !k.col.colours && !k.col.rad && Q->scale == 1.0 && P <= 2 &&
+  bool fast3d = is3d && !k.col.colours && !k.col.rad && !k.col.uvec && Q->scale == 1.0 && P <= 2 &&
                 (double)Q->n * sizeof(T) < 4294967295.0;
   for (int i = 0; i < P; ++i) fast3d = fast3d && grads[i].kind == GK_DIAG;
   // Launch over probes p0 .. p0 + nprobes - 1 of the block with the probe state
@@ -1275,6 +1288,23 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     HIPCHK(launch(MODE_INIT, nb, 0, nullptr, nullptr, nullptr, nullptr));
     HIPCHK(launch(MODE_FIRST, nb, 0, nullptr, nullptr, bufA_r, bufA_p));
     passes += 2;
+    if (k.mat_y) {
+      // second solve of a materialisation: y = w_0 v + sum_{m >= 1} w_m r_m,
+      // r_1 from FIRST, r_{m+1} from the m-th STEP pass (the probes stop where
+      // the first solve's did; their weights are 0 beyond)
+      HIPCHK(launch_mat_accum<double>(k.col.uvec, k.mat_w, k.mat_wstride, 0, nb, n, k.mat_y, true, c->stream));
+      HIPCHK(launch_mat_accum<T>(bufA_r, k.mat_w, k.mat_wstride, 1, nb, n, k.mat_y, false, c->stream));
+      for (int m = 1; m + 1 < k.mat_steps; ++m) {
+        const bool odd = (m % 2) == 1;
+        HIPCHK(odd ? launch(MODE_STEP, nb, 1, bufA_r, bufA_p, bufB_r, bufB_p)
+                   : launch(MODE_STEP, nb, 0, bufB_r, bufB_p, bufA_r, bufA_p));
+        HIPCHK(launch_mat_accum<T>(odd ? bufB_r : bufA_r, k.mat_w, k.mat_wstride, m + 1, nb, n, k.mat_y, false,
+                                   c->stream));
+        ++passes;
+      }
+      HIPCHK(hipStreamSynchronize(c->stream));
+      continue;
+    }
     // the STEP passes of the block in nlanes chains: lane l advances probes
     // lp0[l] .. lp0[l] + lnp[l] - 1 (near-equal shares); lanes 1.. run on
     // streams of their own, forked from and joined to the context stream
@@ -1620,6 +1650,7 @@ static int run_krylov_csr(Call &k, ldq_info *info, double *out_sums) {
   a.colours = k.col.colours;
   a.rad = k.col.rad;
   a.seed = k.col.seed;
+  a.uvec = k.col.uvec;
   a.st = st;
   a.part = part;
 
@@ -1962,6 +1993,113 @@ extern "C" int ldq_logdet_grad(ldq_ctx *c, const ldq_op *Q, int nparams, const l
                                const ldq_options *opts, double *logdet, double *grad, ldq_info *info) {
   if (!logdet || (nparams > 0 && !grad)) return fail(LDQ_E_INVALID, "NULL output");
   return logdet_impl(c, Q, nparams, dQ, opts, logdet, grad, info);
+}
+
+// ------------------------------------------------ f_N(Q) v itself (NEXT row f3)
+// The shifted solutions are combinations of the base CG's residuals (Sec. 2.1,
+// last paragraph: the shifted iterates follow from the base scalars):
+// p^s_0 = r_0, p^s_{k+1} = zeta^s_{k+1} r_{k+1} + beta^s_k p^s_k and
+// x^s = sum_{k < F} alpha^s_k p^s_k, so x^s = sum_m zeta^s_m S^s_m r_m with
+// S^s_m = alpha^s_m + beta^s_m S^s_{m+1}, S^s_F = 0 (F: the terms the shift took
+// before it froze).  Hence f_N(Q) v = Im sum_l a_l x^{s_l} = sum_m w_m r_m with
+// real weights w_m = Im sum_l a_l zeta^{s_l}_m S^{s_l}_m, computed here from the
+// recorded alpha_k, beta_k of a first solve with the same freezing rule as the
+// device; a second, identical solve accumulates the sum.
+static void mat_weights(const double *h, int K, double vnorm2, double tol2, const cplx *sig, const cplx *coef, int N,
+                        double *w) {
+  std::vector<double> alpha(K), beta(std::max(K - 1, 0));
+  for (int m = 0; m < K; ++m) alpha[m] = h[2 * m];
+  for (int m = 0; m + 1 < K; ++m) beta[m] = h[2 * (m + 1) + 1];
+  std::vector<double> gamma(K + 1);
+  gamma[0] = vnorm2;
+  for (int m = 0; m + 1 < K; ++m) gamma[m + 1] = gamma[m] * beta[m];
+  for (int m = 0; m < K; ++m) w[m] = 0.0;
+  using C = std::complex<double>;
+  std::vector<C> zeta(K), as(K), bs(K);
+  for (int l = 0; l < N; ++l) {
+    const C s(sig[l].re, sig[l].im), a(coef[l].re, coef[l].im);
+    C z = 1.0, zp = 1.0;
+    double akm1 = 1.0, bkm1 = 0.0;
+    int F = 0;
+    for (int k = 0; k < K; ++k) {
+      const double ak = alpha[k];
+      const C den = (zp - z) * (ak * bkm1) + zp * akm1 * (1.0 - s * ak);
+      const C zn = z * zp * akm1 / den;
+      const C ratio = zn / z;
+      zeta[k] = z;
+      as[k] = ratio * ak;
+      F = k + 1;
+      if (k + 1 >= K) break;
+      bs[k] = ratio * ratio * beta[k];
+      if (std::norm(zn) * gamma[k + 1] <= tol2 * vnorm2) break;   // frozen after this term
+      zp = z;
+      z = zn;
+      akm1 = ak;
+      bkm1 = beta[k];
+    }
+    C S = 0.0;
+    for (int m = F - 1; m >= 0; --m) {
+      S = as[m] + (m + 1 < F ? bs[m] * S : C(0.0));
+      w[m] += std::imag(a * zeta[m] * S);
+    }
+  }
+}
+
+extern "C" int ldq_logm_apply(ldq_ctx *c, const ldq_op *Q, int nvec, const double *V, double *Y,
+                              const ldq_options *opts, ldq_info *info) {
+  if (!c || !Q || nvec < 1 || !V || !Y) return fail(LDQ_E_INVALID, "invalid arguments");
+  if (Q->kind != OPK_LATTICE) return fail(LDQ_E_UNSUPPORTED, "f_N(Q) v is implemented for lattice operators");
+  ldq_options o;
+  if (opts)
+    o = *opts;
+  else
+    ldq_options_default(&o);
+  // the given vectors are probes 0 .. nvec - 1 of one block, in one chain
+  o.colouring = LDQ_COLOUR_RADEMACHER;
+  o.nrandom = nvec;
+  o.probe_block = 0;
+  o.lanes = 1;
+  Call k{};
+  CHK(prepare_call(k, c, Q, 0, nullptr, &o));
+  k.col.rad = false;
+  k.col.uvec = V;
+  CHK(tune_rows(k));
+  k.lanes = 1;
+  double sums[1 + LDQ_MAXP] = {};
+  ldq_info first{};
+  int st = (k.o.precision == LDQ_MIXED) ? run_krylov<float>(k, &first, sums) : run_krylov<double>(k, &first, sums);
+  if (st != LDQ_OK) return st;
+  // the first solve's coefficients, final states and shifts
+  const int hcap = hist_cap(nvec, k.o.max_iter);
+  std::vector<double> hist((size_t)nvec * hcap * 2);
+  std::vector<ProbeState> pst(nvec);
+  std::vector<cplx> sh(2 * LDQ_MAXN);
+  HIPCHK(hipMemcpyAsync(hist.data(), c->hist.ptr, hist.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(pst.data(), c->pstate.as<ProbeState>() + nvec, nvec * sizeof(ProbeState),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(sh.data(), c->shifts.ptr, sh.size() * sizeof(cplx), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  int kmax = 1;
+  for (const ProbeState &p : pst) kmax = std::max(kmax, p.iter);
+  if (kmax > hcap) return fail(LDQ_E_UNSUPPORTED, "%d iterations exceed the %d the coefficient history holds", kmax, hcap);
+  const int ws = kmax + 1;
+  std::vector<double> w((size_t)nvec * ws, 0.0);
+  for (int j = 0; j < nvec; ++j)
+    mat_weights(hist.data() + (size_t)j * hcap * 2, pst[j].iter, pst[j].vnorm2, k.o.tol * k.o.tol, sh.data(),
+                sh.data() + LDQ_MAXN, k.o.nshifts, w.data() + (size_t)j * ws);
+  CHK(c->matw.reserve(w.size() * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(c->matw.ptr, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  // the second, identical solve accumulates y
+  Call k2 = k;
+  k2.mat_w = c->matw.as<double>();
+  k2.mat_wstride = ws;
+  k2.mat_steps = kmax;
+  k2.mat_y = Y;
+  st = (k.o.precision == LDQ_MIXED) ? run_krylov<float>(k2, nullptr, sums) : run_krylov<double>(k2, nullptr, sums);
+  if (st != LDQ_OK && st != LDQ_E_NO_CONVERGENCE) return st;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (info) *info = first;
+  return LDQ_OK;
 }
 
 extern "C" int ldq_probe_terms(ldq_ctx *c, double *out, int64_t capacity, int64_t *count, int *nparams) {

@@ -124,6 +124,7 @@ struct Pass2D {
   const int32_t *colours;
   int rad;
   uint64_t seed;
+  const double *uvec;       // or given probe vectors, probe-major [probe][n] (FP64)
   // operator
   double kappa2;            // constant shift (SQUARED and unfielded SHIFTED)
   const T *kappa2_field;    // SHIFTED with a field
@@ -148,6 +149,7 @@ struct Pass3D {
   const int32_t *colours;
   int rad;                  // random-sign probes (as in Pass2D)
   uint64_t seed;
+  const double *uvec;       // given probe vectors (as in Pass2D)
   double kappa2;
   const T *kappa2_field;
   double scale;
@@ -212,6 +214,7 @@ struct PassCsr {
   const int32_t *colours;
   int rad;                      // random-sign probes (rad_sign(seed, j, row)); colours unused
   uint64_t seed;
+  const double *uvec;           // given probe vectors [probe][n] (FP64); colours unused
   const ProbeState *st;
   const T *r_in, *p_in;
   T *r_out, *p_out;

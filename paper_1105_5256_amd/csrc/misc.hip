@@ -355,3 +355,32 @@ hipError_t launch_to_float(const double *src, float *dst, size_t n, hipStream_t 
 }
 
 }  // namespace ldq
+
+namespace ldq {
+// y[j][i] (= or +=) w[j][m] x[j][i] over nb vectors of n entries (the
+// accumulation of f_N(Q) v = sum_m w_m r_m from the Krylov residuals).
+template <typename S>
+__global__ void mat_accum_kernel(const S *x, const double *w, int wstride, int m, int nb, int64_t n, double *y,
+                                 int init) {
+  const size_t total = (size_t)nb * (size_t)n;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(t / (size_t)n);
+    const double c = w[(size_t)j * wstride + m];
+    y[t] = (init ? 0.0 : y[t]) + c * (double)x[t];
+  }
+}
+
+template <typename S>
+hipError_t launch_mat_accum(const S *x, const double *w, int wstride, int m, int nb, int64_t n, double *y, bool init,
+                            hipStream_t s) {
+  const size_t total = (size_t)nb * (size_t)n;
+  if (total == 0) return hipSuccess;
+  const int blocks = (int)std::min<size_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(mat_accum_kernel<S>, dim3(blocks), dim3(256), 0, s, x, w, wstride, m, nb, n, y, init ? 1 : 0);
+  return hipGetLastError();
+}
+template hipError_t launch_mat_accum<float>(const float *, const double *, int, int, int, int64_t, double *, bool,
+                                            hipStream_t);
+template hipError_t launch_mat_accum<double>(const double *, const double *, int, int, int, int64_t, double *, bool,
+                                             hipStream_t);
+}  // namespace ldq

@@ -124,6 +124,7 @@ __global__ __launch_bounds__(64) void pass2d_kernel(Pass2D<T> a) {
   // class, -1 / +1 for random signs (0 outside the lattice)
   auto mine_at = [&](int y, int ay) -> double {
     if (a.rad) return (xin && y >= 0 && y < ny) ? rad_sign(a.seed, colour, (int64_t)y * nx + x) : 0.0;
+    if (a.uvec) return (xin && y >= 0 && y < ny) ? a.uvec[(size_t)colour * n + (size_t)y * nx + x] : 0.0;
     if (C > 0) {
       int v = cx + ay;
       v -= (v >= C) ? C : 0;

@@ -29,6 +29,7 @@ __device__ inline int colour3(const Pass3D<T> &a, int x, int y, int z) {
 template <typename T>
 __device__ inline double probe3(const Pass3D<T> &a, int colour, int x, int y, int z) {
   if (a.rad) return rad_sign(a.seed, colour, ((int64_t)z * a.ny + y) * a.nx + x);
+  if (a.uvec) return a.uvec[((size_t)colour * a.nz + z) * a.ny * a.nx + (size_t)y * a.nx + x];
   return colour3(a, x, y, z) == colour ? 1.0 : 0.0;
 }
 

@@ -244,13 +244,14 @@ __global__ __launch_bounds__(256) void csr_pass_a_kernel(PassCsr<T> a) {
     load_slice<T, W, NG>(a, ws, R);
     if constexpr (FIRST) {
 #pragma unroll
-      for (int k = 0; k < W; ++k) ccol[k] = a.rad ? 0 : a.colours[R.off[k] / (uint32_t)sizeof(T)];
+      for (int k = 0; k < W; ++k) ccol[k] = (a.rad || a.uvec) ? 0 : a.colours[R.off[k] / (uint32_t)sizeof(T)];
     }
   }
-  const int mycol = a.rad ? 0 : a.colours[ws.row];
+  const int mycol = (a.rad || a.uvec) ? 0 : a.colours[ws.row];
   // entry of probe j (colour cj) at a row: 0 / 1 for a colour class, -1 / +1
   // for random signs
   auto probe_at = [&](int cj, int64_t row, int colour_of_row) -> double {
+    if (a.uvec) return a.uvec[(size_t)cj * a.n + row];
     return a.rad ? rad_sign(a.seed, cj, row) : (colour_of_row == cj ? 1.0 : 0.0);
   };
   constexpr int NQ = 2 + NG;
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(256) void csr_pass_a_kernel(PassCsr<T> a) {
         const int32_t c = a.col[e];
         double x;
         if constexpr (FIRST)
-          x = probe_at(cj, c, a.rad ? 0 : a.colours[c]);
+          x = probe_at(cj, c, (a.rad || a.uvec) ? 0 : a.colours[c]);
         else
           x = fma(beta, (double)pb[c], (double)rb[c]);
         q = fma(a.val[e], x, q);
@@ -354,11 +355,12 @@ __global__ __launch_bounds__(256) void csr_pass_b_kernel(PassCsr<T> a) {
     load_slice<T, W, 0>(a, ws, R);
     if constexpr (INIT) {
 #pragma unroll
-      for (int k = 0; k < W; ++k) ccol[k] = a.rad ? 0 : a.colours[R.off[k] / (uint32_t)sizeof(T)];
+      for (int k = 0; k < W; ++k) ccol[k] = (a.rad || a.uvec) ? 0 : a.colours[R.off[k] / (uint32_t)sizeof(T)];
     }
   }
-  const int mycol = a.rad ? 0 : a.colours[ws.row];
+  const int mycol = (a.rad || a.uvec) ? 0 : a.colours[ws.row];
   auto probe_at = [&](int cj, int64_t row, int colour_of_row) -> double {
+    if (a.uvec) return a.uvec[(size_t)cj * a.n + row];
     return a.rad ? rad_sign(a.seed, cj, row) : (colour_of_row == cj ? 1.0 : 0.0);
   };
   for (int c0 = 0; c0 < a.nprobes; c0 += 64) {
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(256) void csr_pass_b_kernel(PassCsr<T> a) {
       for (int k = 0; k < ws.w; ++k) {
         const int64_t e = ws.off + (int64_t)k * 64 + ws.lane;
         const int32_t c = a.col[e];
-        const double x = INIT ? probe_at(cj, c, a.rad ? 0 : a.colours[c]) : (double)xb[c];
+        const double x = INIT ? probe_at(cj, c, (a.rad || a.uvec) ? 0 : a.colours[c]) : (double)xb[c];
         s = fma(a.val[e], x, s);
       }
     }

@@ -106,6 +106,7 @@ _SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(ldq_info)]),
     "ldq_probe_terms": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_int)]),
+    "ldq_logm_apply": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P]),
     "ldq_logdet_batched": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int, _P, ctypes.POINTER(ldq_options),
                                           _P, _P, _P]),
 }
@@ -302,6 +303,22 @@ def ldq_probe_terms(ctx):
     _check(load().ldq_probe_terms(ctx, _ptr(out), len(out), ctypes.byref(cnt), ctypes.byref(npar)),
            "ldq_probe_terms")
     return out.reshape(cnt.value, 1 + npar.value)
+
+
+def ldq_logm_apply(ctx, Q, V, opts=None):
+    """f_N(Q) V for the rows of V (a torch float64 CUDA tensor, nvec x n, contiguous):
+    returns (Y of the same shape on the same device, info dict of the first solve)."""
+    import torch
+    if V.dim() == 1:
+        V = V[None]
+    if V.dtype != torch.float64 or not V.is_cuda or not V.is_contiguous():
+        raise ValueError("V must be a contiguous float64 CUDA tensor")
+    Y = torch.empty_like(V)
+    opts = opts if opts is not None else ldq_options_default()
+    info = ldq_info()
+    _check(load().ldq_logm_apply(ctx, Q, V.shape[0], ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                 ctypes.byref(opts), ctypes.byref(info)), "ldq_logm_apply")
+    return Y, info.as_dict()
 
 
 def ldq_logdet_batched(ctx, Qs, dQs=None, opts=None):
