@@ -2049,6 +2049,16 @@ extern "C" int ldq_logm_apply(ldq_ctx *c, const ldq_op *Q, int nvec, const doubl
                               const ldq_options *opts, ldq_info *info) {
   if (!c || !Q || nvec < 1 || !V || !Y) return fail(LDQ_E_INVALID, "invalid arguments");
   if (Q->kind != OPK_LATTICE) return fail(LDQ_E_UNSUPPORTED, "f_N(Q) v is implemented for lattice operators");
+  CHK(set_device(c));
+  // V and Y are read and written by kernels: device (or managed) memory only
+  for (const void *ptr : {(const void *)V, (const void *)Y}) {
+    hipPointerAttribute_t at{};
+    const hipError_t e = hipPointerGetAttributes(&at, ptr);
+    if (e != hipSuccess || (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)) {
+      (void)hipGetLastError();
+      return fail(LDQ_E_INVALID, "V and Y must be device memory");
+    }
+  }
   ldq_options o;
   if (opts)
     o = *opts;

@@ -67,3 +67,12 @@ def test_logm_apply_error_paths(ctx):
     with pytest.raises(ldq.LdqError) as e:
         ldq.ldq_logm_apply(ctx.handle, C, torch.ones(1, 4, dtype=torch.float64, device="cuda"))
     assert e.value.status == ldq.LDQ_E_UNSUPPORTED
+    # host memory is refused through the C ABI (the kernels could not read it)
+    import ctypes
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, (6, 5), ldq.LDQ_SHIFTED_LAPLACIAN, 0.5))
+    host = np.ones(30)
+    out = np.zeros(30)
+    opts = ldq.ldq_options_default()
+    st = ldq.load().ldq_logm_apply(ctx.handle, Q, 1, host.ctypes.data_as(ctypes.c_void_p),
+                                   out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts), None)
+    assert st == ldq.LDQ_E_INVALID
