@@ -68,3 +68,20 @@ def grad_probing_dst(shape, kappa2, power, colours, dQs):
         for i, dQ in enumerate(dQs):
             terms[j, i] = x @ (dQ @ v)
     return terms.sum(axis=0), terms
+
+
+def grad_estimator_rational(Q, dQs, colours, sigma, coef):
+    """The derivative of the probing estimate E(Q; c) of eq. (7) with the shifts
+    held fixed: dE/d eta_i = -sum_j Im sum_l c_l (x_jl)^T dQ_i x_jl with
+    x_jl = (Q - sigma_l I)^{-1} v_j (d(A^{-1}) = -A^{-1} dA A^{-1}; Q - sigma_l I
+    is complex symmetric, so no conjugation).  Returns (g, per-class terms)."""
+    P, _ = probes(colours)
+    Qc = sp.csc_matrix(Q, dtype=np.complex128)
+    n = Qc.shape[0]
+    eye = sp.identity(n, dtype=np.complex128, format="csc")
+    terms = np.zeros((P.shape[1], len(dQs)))
+    for s, c in zip(sigma, coef):
+        X = spla.splu((Qc - s * eye).tocsc()).solve(P.astype(np.complex128))
+        for i, dQ in enumerate(dQs):
+            terms[:, i] -= np.imag(c * np.sum(X * (dQ @ X), axis=0))
+    return terms.sum(axis=0), terms

@@ -1,5 +1,6 @@
 """Pins of oracle/gradient.py (CPU only)."""
 import numpy as np
+import scipy.sparse as sp
 
 from oracle import colouring, exact, gradient, lattice
 from paper_1105_5256_amd import workloads
@@ -49,3 +50,24 @@ def test_field_model_gradient_matches_finite_differences():
     assert np.allclose(fd, exact_g, rtol=1e-6)
     G, _ = gradient.grad_probing(Q, dQ, np.arange(Q.shape[0]))
     assert np.allclose(G, exact_g, rtol=1e-11)
+
+
+def test_estimator_derivative_matches_finite_differences():
+    # the derivative of the probing estimate with fixed shifts, against central
+    # differences of the estimate itself (oracle.estimator.estimator_rational_direct)
+    from oracle import colouring, estimator, shifts
+    shape = (9, 8)
+    C, co = colouring.find_modular(2, 2)
+    col = colouring.modular_colouring(shape, C, co)
+    lam = np.linalg.eigvalsh(lattice.shifted_laplacian(shape, 0.4).toarray())
+    sig, coef = shifts.log_shifts(lam[0] * 0.9, lam[-1] * 1.1, 20)
+    d = np.linspace(0.5, 1.5, 72)
+    g, _ = gradient.grad_estimator_rational(lattice.shifted_laplacian(shape, 0.4), [sp.diags(d)], col, sig, coef)
+    h = 1e-5
+    Ep, _ = estimator.estimator_rational_direct(lattice.shifted_laplacian(shape, 0.4) + h * sp.diags(d), col, sig, coef)
+    Em, _ = estimator.estimator_rational_direct(lattice.shifted_laplacian(shape, 0.4) - h * sp.diags(d), col, sig, coef)
+    assert abs(g[0] - (Ep - Em) / (2 * h)) < 1e-7 * abs(g[0])
+    # identity probing: the derivative of the rational log det, close to tr(Q^-1 dQ)
+    ident = np.arange(72)
+    gi, _ = gradient.grad_estimator_rational(lattice.shifted_laplacian(shape, 0.4), [sp.diags(d)], ident, sig, coef)
+    assert abs(gi[0] - gradient.grad_dense(lattice.shifted_laplacian(shape, 0.4), sp.diags(d))) < 1e-6 * abs(gi[0])
