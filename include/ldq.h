@@ -178,6 +178,13 @@ typedef struct {
                                    numbered x + nx (y + ny z)); the result is the mean over probes,
                                    (1/s) sum_j v_j^T log(Q) v_j, and likewise the gradient */
   uint64_t seed;                /* LDQ_COLOUR_RADEMACHER: generator state */
+  int consistent_grad;          /* 0: grad_i = sum_j x_j^T dQ_i v_j (x_j = Q^{-1} v_j), the probing
+                                   estimate of tr(Q^{-1} dQ_i); 1: the exact derivative of the
+                                   log det estimate with the shifts held fixed,
+                                   -sum_j Im sum_l c_l (x^l_j)^T dQ_i x^l_j with x^l_j = (Q - sigma_l I)^{-1}
+                                   v_j, from a second Krylov solve that accumulates the shifted
+                                   solutions (N complex vectors per probe; lattice Q, derivatives
+                                   diagonal or scaled shifted Laplacians; at most 8192 iterations) */
 } ldq_options;
 
 /* launch_mode: AUTO and GRAPH capture one chunk of Krylov pass launches into a HIP graph (on a

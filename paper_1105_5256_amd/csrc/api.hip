@@ -62,6 +62,11 @@ template <typename T> hipError_t launch_batch2d(const Batch2D<T> &, int, bool, i
 template <typename S>
 hipError_t launch_mat_accum(const S *x, const double *w, int wstride, int m, int nb, int64_t n, double *y, bool init,
                             hipStream_t s);
+template <typename S>
+hipError_t launch_mat_accum_shifts(const S *x, const cplx *c, int cstride, int m, int N, int nb, int64_t n, cplx *z,
+                                   bool init, hipStream_t s);
+hipError_t launch_lattice_bilinear(const cplx *z, int nv, int nx, int ny, int nz, bool diag, double scale, double kd,
+                                   const double *field, cplx *out, hipStream_t s);
 hipError_t launch_batch_compact(const FieldDesc *, const int32_t *, int, const ProbeState *, ProbeState *, WorkItem *,
                                 int *, hipStream_t);
 }  // namespace ldq
@@ -147,6 +152,7 @@ struct ldq_ctx {
   DevBuf vec, partials, pstate, sstate, shifts, classes, terms, stats, sums, misc, colbuf, jpkey, jpmask, hist;
   DevBuf bfields, bitems, bwork, blohi;   // batched lattice passes
   DevBuf matw;                            // weights of a materialisation of f_N(Q) v
+  DevBuf matc, matz, matq;                // consistent gradient: coefficients, shifted solutions, forms
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evp[2] = {nullptr, nullptr};   // convergence polls
   int *hpin = nullptr;                      // pinned host copies of the device counters
@@ -251,7 +257,7 @@ extern "C" void ldq_destroy(ldq_ctx *c) {
   hipStreamSynchronize(c->stream);
   for (DevBuf *b : {&c->vec, &c->partials, &c->pstate, &c->sstate, &c->shifts, &c->classes,
                     &c->terms, &c->stats, &c->sums, &c->misc, &c->colbuf, &c->jpkey, &c->jpmask, &c->hist,
-                    &c->bfields, &c->bitems, &c->bwork, &c->blohi, &c->matw})
+                    &c->bfields, &c->bitems, &c->bwork, &c->blohi, &c->matw, &c->matc, &c->matz, &c->matq})
     b->release();
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
@@ -887,6 +893,10 @@ struct Call {
   const double *mat_w;
   int mat_wstride, mat_steps;
   double *mat_y;
+  // ... or the shifted solutions z_jl = sum_m c[j][m][l] r_m themselves
+  const cplx *mat_c;
+  int mat_cstride;
+  cplx *mat_z;
   double *tune_ms;   // non-null: a timing run of the autotuner (a few passes of the first probe block)
 };
 
@@ -1288,18 +1298,28 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     HIPCHK(launch(MODE_INIT, nb, 0, nullptr, nullptr, nullptr, nullptr));
     HIPCHK(launch(MODE_FIRST, nb, 0, nullptr, nullptr, bufA_r, bufA_p));
     passes += 2;
-    if (k.mat_y) {
-      // second solve of a materialisation: y = w_0 v + sum_{m >= 1} w_m r_m,
-      // r_1 from FIRST, r_{m+1} from the m-th STEP pass (the probes stop where
-      // the first solve's did; their weights are 0 beyond)
-      HIPCHK(launch_mat_accum<double>(k.col.uvec, k.mat_w, k.mat_wstride, 0, nb, n, k.mat_y, true, c->stream));
-      HIPCHK(launch_mat_accum<T>(bufA_r, k.mat_w, k.mat_wstride, 1, nb, n, k.mat_y, false, c->stream));
+    if (k.mat_y || k.mat_z) {
+      // second solve of a materialisation: y = w_0 v + sum_{m >= 1} w_m r_m
+      // (or each shift's z_l = sum_m c_ml r_m), r_0 = p_0 = v and r_1 from
+      // FIRST, r_{m+1} from the m-th STEP pass (the probes stop where the
+      // first solve's did; their coefficients are 0 beyond)
+      const int N = k.o.nshifts;
+      if (k.mat_y) {
+        HIPCHK(launch_mat_accum<double>(k.col.uvec, k.mat_w, k.mat_wstride, 0, nb, n, k.mat_y, true, c->stream));
+        HIPCHK(launch_mat_accum<T>(bufA_r, k.mat_w, k.mat_wstride, 1, nb, n, k.mat_y, false, c->stream));
+      } else {
+        HIPCHK(launch_mat_accum_shifts<T>(bufA_p, k.mat_c, k.mat_cstride, 0, N, nb, n, k.mat_z, true, c->stream));
+        HIPCHK(launch_mat_accum_shifts<T>(bufA_r, k.mat_c, k.mat_cstride, 1, N, nb, n, k.mat_z, false, c->stream));
+      }
       for (int m = 1; m + 1 < k.mat_steps; ++m) {
         const bool odd = (m % 2) == 1;
         HIPCHK(odd ? launch(MODE_STEP, nb, 1, bufA_r, bufA_p, bufB_r, bufB_p)
                    : launch(MODE_STEP, nb, 0, bufB_r, bufB_p, bufA_r, bufA_p));
-        HIPCHK(launch_mat_accum<T>(odd ? bufB_r : bufA_r, k.mat_w, k.mat_wstride, m + 1, nb, n, k.mat_y, false,
-                                   c->stream));
+        const T *rm = odd ? bufB_r : bufA_r;
+        if (k.mat_y)
+          HIPCHK(launch_mat_accum<T>(rm, k.mat_w, k.mat_wstride, m + 1, nb, n, k.mat_y, false, c->stream));
+        else
+          HIPCHK(launch_mat_accum_shifts<T>(rm, k.mat_c, k.mat_cstride, m + 1, N, nb, n, k.mat_z, false, c->stream));
         ++passes;
       }
       HIPCHK(hipStreamSynchronize(c->stream));
@@ -1947,11 +1967,84 @@ static int tune_rows(Call &k) {
   return LDQ_OK;
 }
 
+// The derivative of the probing estimate with the shifts fixed (NEXT row
+// f3): dE/d eta_i = -sum_j Im sum_l c_l (x^l_j)^T dQ_i x^l_j.  The shifted
+// solutions x^l_j = sum_m zeta^l_m S^l_m r_m are accumulated by a second solve
+// from the coefficients of the first (as for f_N(Q) v), then one bilinear form
+// per (probe, shift) and derivative.  Replaces grad[0 .. nparams).
+static void mat_weights(const double *h, int K, double vnorm2, double tol2, const cplx *sig, const cplx *coef, int N,
+                        double *w, cplx *cc);
+static int consistent_gradient(Call &k, double *grad) {
+  ldq_ctx *c = k.c;
+  ldq_op *Q = k.Q;
+  const int nb = (int)k.classes.size();
+  const int N = k.o.nshifts;
+  const int64_t n = Q->n;
+  const int hcap = hist_cap(nb, k.o.max_iter);
+  std::vector<double> hist((size_t)nb * hcap * 2);
+  std::vector<ProbeState> pst(nb);
+  std::vector<cplx> sh(2 * LDQ_MAXN);
+  HIPCHK(hipMemcpyAsync(hist.data(), c->hist.ptr, hist.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(pst.data(), c->pstate.as<ProbeState>() + nb, nb * sizeof(ProbeState), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(sh.data(), c->shifts.ptr, sh.size() * sizeof(cplx), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  int kmax = 1;
+  for (const ProbeState &p : pst) kmax = std::max(kmax, p.iter);
+  if (kmax > hcap) return fail(LDQ_E_UNSUPPORTED, "%d iterations exceed the %d the coefficient history holds", kmax, hcap);
+  const int cstride = (kmax + 1) * N;
+  std::vector<cplx> cc((size_t)nb * cstride, cmk(0.0, 0.0));
+  std::vector<double> w(kmax + 1);
+  for (int j = 0; j < nb; ++j)
+    mat_weights(hist.data() + (size_t)j * hcap * 2, pst[j].iter, pst[j].vnorm2, k.o.tol * k.o.tol, sh.data(),
+                sh.data() + LDQ_MAXN, N, w.data(), cc.data() + (size_t)j * cstride);
+  CHK(c->matc.reserve(cc.size() * sizeof(cplx)));
+  CHK(c->matz.reserve((size_t)nb * N * (size_t)n * sizeof(cplx)));
+  CHK(c->matq.reserve((size_t)nb * N * sizeof(cplx)));
+  HIPCHK(hipMemcpyAsync(c->matc.ptr, cc.data(), cc.size() * sizeof(cplx), hipMemcpyHostToDevice, c->stream));
+  Call k2 = k;
+  k2.mat_c = c->matc.as<cplx>();
+  k2.mat_cstride = cstride;
+  k2.mat_z = c->matz.as<cplx>();
+  k2.mat_steps = kmax;
+  double sums[1 + LDQ_MAXP];
+  const int st = (k.o.precision == LDQ_MIXED) ? run_krylov<float>(k2, nullptr, sums) : run_krylov<double>(k2, nullptr, sums);
+  if (st != LDQ_OK && st != LDQ_E_NO_CONVERGENCE) return st;
+  std::vector<cplx> q((size_t)nb * N);
+  for (int i = 0; i < k.nparams; ++i) {
+    const ldq_op *d = k.dQ[i];
+    const bool diag = d->kind == OPK_DIAG;
+    HIPCHK(launch_lattice_bilinear(c->matz.as<cplx>(), nb * N, (int)Q->shape[0], (int)Q->shape[1],
+                                   Q->ndim == 3 ? (int)Q->shape[2] : 1, diag, d->scale, diag ? 0.0 : d->kappa2,
+                                   d->field, c->matq.as<cplx>(), c->stream));
+    HIPCHK(hipMemcpyAsync(q.data(), c->matq.ptr, q.size() * sizeof(cplx), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double g = 0.0;
+    for (int j = 0; j < nb; ++j)
+      for (int l = 0; l < N; ++l) {
+        const cplx a = sh[LDQ_MAXN + l], z = q[(size_t)j * N + l];
+        g -= a.re * z.im + a.im * z.re;   // Im(a z)
+      }
+    grad[i] = g;
+  }
+  return LDQ_OK;
+}
+
 static int logdet_impl(ldq_ctx *c, const ldq_op *Q, int nparams, const ldq_op *const *dQ, const ldq_options *opts,
                        double *logdet, double *grad, ldq_info *info) {
   auto t0 = std::chrono::steady_clock::now();
   Call k{};
   CHK(prepare_call(k, c, Q, nparams, dQ, opts));
+  const bool consistent = k.o.consistent_grad && nparams > 0;
+  if (consistent) {
+    if (k.Q->kind != OPK_LATTICE) return fail(LDQ_E_UNSUPPORTED, "the consistent gradient needs a lattice Q");
+    for (int i = 0; i < nparams; ++i) {
+      const ldq_op *d = k.dQ[i];
+      if (!(d->kind == OPK_DIAG || (d->kind == OPK_LATTICE && d->lkind == LDQ_SHIFTED_LAPLACIAN)))
+        return fail(LDQ_E_UNSUPPORTED, "the consistent gradient takes diagonal or shifted-Laplacian derivatives");
+    }
+    k.o.probe_block = 0;   // one block: its coefficient history covers every probe
+  }
   double sums[1 + LDQ_MAXP] = {};
   ldq_info tmp{};
   int st;
@@ -1959,9 +2052,11 @@ static int logdet_impl(ldq_ctx *c, const ldq_op *Q, int nparams, const ldq_op *c
     st = (k.o.precision == LDQ_MIXED) ? run_krylov_csr<float>(k, &tmp, sums) : run_krylov_csr<double>(k, &tmp, sums);
   } else {
     CHK(tune_rows(k));
+    if (consistent) k.lanes = 1;
     st = (k.o.precision == LDQ_MIXED) ? run_krylov<float>(k, &tmp, sums) : run_krylov<double>(k, &tmp, sums);
   }
   if (st != LDQ_OK && st != LDQ_E_NO_CONVERGENCE) return st;
+  if (consistent && st == LDQ_OK) CHK(consistent_gradient(k, sums + 1));
   if (k.col.rad) {
     // Hutchinson's estimator: the mean over the s probes, and the standard
     // error of that mean from the per-probe terms
@@ -2006,7 +2101,7 @@ extern "C" int ldq_logdet_grad(ldq_ctx *c, const ldq_op *Q, int nparams, const l
 // recorded alpha_k, beta_k of a first solve with the same freezing rule as the
 // device; a second, identical solve accumulates the sum.
 static void mat_weights(const double *h, int K, double vnorm2, double tol2, const cplx *sig, const cplx *coef, int N,
-                        double *w) {
+                        double *w, cplx *cc = nullptr) {
   std::vector<double> alpha(K), beta(std::max(K - 1, 0));
   for (int m = 0; m < K; ++m) alpha[m] = h[2 * m];
   for (int m = 0; m + 1 < K; ++m) beta[m] = h[2 * (m + 1) + 1];
@@ -2014,6 +2109,8 @@ static void mat_weights(const double *h, int K, double vnorm2, double tol2, cons
   gamma[0] = vnorm2;
   for (int m = 0; m + 1 < K; ++m) gamma[m + 1] = gamma[m] * beta[m];
   for (int m = 0; m < K; ++m) w[m] = 0.0;
+  if (cc)
+    for (int m = 0; m < K * N; ++m) cc[m] = cmk(0.0, 0.0);
   using C = std::complex<double>;
   std::vector<C> zeta(K), as(K), bs(K);
   for (int l = 0; l < N; ++l) {
@@ -2041,6 +2138,7 @@ static void mat_weights(const double *h, int K, double vnorm2, double tol2, cons
     for (int m = F - 1; m >= 0; --m) {
       S = as[m] + (m + 1 < F ? bs[m] * S : C(0.0));
       w[m] += std::imag(a * zeta[m] * S);
+      if (cc) cc[(size_t)m * N + l] = cmk(std::real(zeta[m] * S), std::imag(zeta[m] * S));
     }
   }
 }

@@ -384,3 +384,99 @@ template hipError_t launch_mat_accum<float>(const float *, const double *, int, 
 template hipError_t launch_mat_accum<double>(const double *, const double *, int, int, int, int64_t, double *, bool,
                                              hipStream_t);
 }  // namespace ldq
+
+namespace ldq {
+// z[j][l][i] (= or +=) c[j][m][l] x[j][i] for the N shifts l: the shifted
+// solutions x^l_j = sum_m c[j][m][l] r_m of probe j, accumulated from its
+// residuals (complex coefficients, complex vectors [probe][shift][n]).
+template <typename S>
+__global__ void mat_accum_shifts_kernel(const S *x, const cplx *c, int cstride, int m, int N, int nb, int64_t n,
+                                        cplx *z, int init) {
+  const size_t total = (size_t)nb * (size_t)n;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(t / (size_t)n);
+    const size_t i = t - (size_t)j * (size_t)n;
+    const double xv = (double)x[t];
+    const cplx *cj = c + (size_t)j * cstride + (size_t)m * N;
+    cplx *zj = z + (size_t)j * N * (size_t)n + i;
+    for (int l = 0; l < N; ++l) {
+      cplx acc = init ? cmk(0.0, 0.0) : zj[(size_t)l * n];
+      acc.re += cj[l].re * xv;
+      acc.im += cj[l].im * xv;
+      zj[(size_t)l * n] = acc;
+    }
+  }
+}
+
+template <typename S>
+hipError_t launch_mat_accum_shifts(const S *x, const cplx *c, int cstride, int m, int N, int nb, int64_t n, cplx *z,
+                                   bool init, hipStream_t s) {
+  const size_t total = (size_t)nb * (size_t)n;
+  if (total == 0) return hipSuccess;
+  const int blocks = (int)std::min<size_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(mat_accum_shifts_kernel<S>, dim3(blocks), dim3(256), 0, s, x, c, cstride, m, N, nb, n, z,
+                     init ? 1 : 0);
+  return hipGetLastError();
+}
+template hipError_t launch_mat_accum_shifts<float>(const float *, const cplx *, int, int, int, int, int64_t, cplx *,
+                                                   bool, hipStream_t);
+template hipError_t launch_mat_accum_shifts<double>(const double *, const cplx *, int, int, int, int, int64_t, cplx *,
+                                                    bool, hipStream_t);
+
+// out[v] = z_v^T dQ z_v (complex bilinear, no conjugation) for the vectors
+// v = 0 .. nv - 1 of z (n entries each) and a lattice derivative operator:
+// diag (scale * d) or scale * (kd I + L) with Dirichlet L on nx x ny x nz.
+// One workgroup per vector; the workgroup's sum is taken in a fixed order.
+__global__ void lattice_bilinear_kernel(const cplx *z, int nx, int ny, int nz, int diag, double scale, double kd,
+                                        const double *field, cplx *out) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  const cplx *zz = z + (size_t)blockIdx.x * (size_t)n;
+  const int dim = nz > 1 ? 3 : 2;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const cplx zi = zz[i];
+    double sr, si;
+    if (diag) {
+      sr = scale * field[i] * zi.re;
+      si = scale * field[i] * zi.im;
+    } else {
+      const int64_t x = i % nx, y = (i / nx) % ny, zc = i / ((int64_t)nx * ny);
+      const double k = field ? field[i] : kd;
+      double nr = 0.0, ni = 0.0;
+      auto add = [&](int64_t o) { nr += zz[o].re; ni += zz[o].im; };
+      if (x > 0) add(i - 1);
+      if (x + 1 < nx) add(i + 1);
+      if (y > 0) add(i - nx);
+      if (y + 1 < ny) add(i + nx);
+      if (dim == 3) {
+        if (zc > 0) add(i - (int64_t)nx * ny);
+        if (zc + 1 < nz) add(i + (int64_t)nx * ny);
+      }
+      sr = scale * ((k + 2.0 * dim) * zi.re - nr);
+      si = scale * ((k + 2.0 * dim) * zi.im - ni);
+    }
+    re += zi.re * sr - zi.im * si;
+    im += zi.re * si + zi.im * sr;
+  }
+  __shared__ double sre[256], sim[256];
+  sre[threadIdx.x] = re;
+  sim[threadIdx.x] = im;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sre[threadIdx.x] += sre[threadIdx.x + w];
+      sim[threadIdx.x] += sim[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = cmk(sre[0], sim[0]);
+}
+
+hipError_t launch_lattice_bilinear(const cplx *z, int nv, int nx, int ny, int nz, bool diag, double scale, double kd,
+                                   const double *field, cplx *out, hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lattice_bilinear_kernel, dim3(nv), dim3(256), 0, s, z, nx, ny, nz, diag ? 1 : 0, scale, kd, field,
+                     out);
+  return hipGetLastError();
+}
+}  // namespace ldq

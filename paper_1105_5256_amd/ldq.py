@@ -46,6 +46,7 @@ class ldq_options(ctypes.Structure):
         ("lanes", ctypes.c_int),
         ("nrandom", ctypes.c_int),
         ("seed", ctypes.c_uint64),
+        ("consistent_grad", ctypes.c_int),
     ]
 
 
