@@ -21,6 +21,8 @@
 namespace ldq {
 // launchers (pass2d.hip, pass3d.hip, misc.hip, colour.hip)
 template <typename T> hipError_t launch_pass2d(const Pass2D<T> &, bool, bool, bool, hipStream_t);
+hipError_t launch_rad_masks(uint64_t *out, uint64_t seed, int first, int nprobes, int nx, int ny, bool squared,
+                            hipStream_t stream);
 template <typename T> hipError_t launch_pass3d(const Pass3D<T> &, bool, hipStream_t);
 void pass2d_tiles(int nx, int ny, bool squared, int rows, int *tiles_x, int *ntiles);
 int pass2d_rows(bool squared, int want);
@@ -153,6 +155,8 @@ struct ldq_ctx {
   DevBuf bfields, bitems, bwork, blohi;   // batched lattice passes
   DevBuf matw;                            // weights of a materialisation of f_N(Q) v
   DevBuf matc, matz, matq;                // consistent gradient: coefficients, shifted solutions, forms
+  DevBuf radmask;                         // sign masks of random-sign probes (specialised 2-D pass)
+  uint64_t radmask_key[5] = {};           // seed, probes, nx, ny, squared of the masks held
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evp[2] = {nullptr, nullptr};   // convergence polls
   int *hpin = nullptr;                      // pinned host copies of the device counters
@@ -257,7 +261,8 @@ extern "C" void ldq_destroy(ldq_ctx *c) {
   hipStreamSynchronize(c->stream);
   for (DevBuf *b : {&c->vec, &c->partials, &c->pstate, &c->sstate, &c->shifts, &c->classes,
                     &c->terms, &c->stats, &c->sums, &c->misc, &c->colbuf, &c->jpkey, &c->jpmask, &c->hist,
-                    &c->bfields, &c->bitems, &c->bwork, &c->blohi, &c->matw, &c->matc, &c->matz, &c->matq})
+                    &c->bfields, &c->bitems, &c->bwork, &c->blohi, &c->matw, &c->matc, &c->matz, &c->matq,
+                    &c->radmask})
     b->release();
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
@@ -1227,13 +1232,34 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   // the specialised 2-D pass: modular colouring, constant kappa2, gradient 0 a
   // shifted Laplacian with a constant shift, gradient 1 (with observations)
   // the observation gram of Q's own observations
-  bool fast2d = !is3d && !k.col.colours && !k.col.rad && !k.col.uvec && !kfield && Q->scale == 1.0 &&
+  bool fast2d = !is3d && !k.col.colours && !k.col.uvec && !kfield && Q->scale == 1.0 &&
                 (double)Q->n * sizeof(T) * (has_obs ? 9.0 : 1.0) < 4294967295.0;
   if (P >= 1) fast2d = fast2d && grads[0].kind == GK_SHIFTED && !grads[0].field;
   if (P >= 2)
     fast2d = fast2d && has_obs && grads[1].kind == GK_OBS && k.dQ[1]->obs_hash == Q->obs_hash &&
              k.dQ[1]->nobs == Q->nobs;
   if (P >= 2 && fast2d) a2.grad[1].scale = k.dQ[1]->tau;
+  // random-sign probes take the specialised pass through per-row sign masks
+  // of its strips (one 64-bit word per probe, row and strip; kept on the
+  // context): without observations and for at most 64 MiB of masks
+  const uint64_t *rmask = nullptr;
+  if (fast2d && k.col.rad) {
+    const size_t words = (size_t)nprobes_total * (size_t)Q->shape[1] * (size_t)tiles_x;
+    if (has_obs || words * 8 > ((size_t)64 << 20)) {
+      fast2d = false;
+    } else {
+      const uint64_t key[5] = {k.col.seed, (uint64_t)nprobes_total, (uint64_t)Q->shape[0], (uint64_t)Q->shape[1],
+                               (uint64_t)sq};
+      if (!c->radmask.ptr || memcmp(key, c->radmask_key, sizeof key) != 0) {
+        memset(c->radmask_key, 0, sizeof c->radmask_key);
+        CHK(c->radmask.reserve(words * 8));
+        HIPCHK(launch_rad_masks(c->radmask.as<uint64_t>(), k.col.seed, 0, nprobes_total, (int)Q->shape[0],
+                                (int)Q->shape[1], sq, c->stream));
+        memcpy(c->radmask_key, key, sizeof key);
+      }
+      rmask = c->radmask.as<uint64_t>();
+    }
+  }
   // the specialised 3-D pass: modular colouring, scale 1, at most two diagonal
   // derivative operators, 32-bit byte offsets
   bool fast3d = is3d && !k.col.colours && !k.col.rad && !k.col.uvec && Q->scale == 1.0 && P <= 2 &&
@@ -1245,6 +1271,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   // chunk is captured).  Every per-probe array is probe-major, so a part of
   // the block is the whole-block launch with its base pointers advanced.
   hipStream_t ls = c->stream;
+  int blk_first = 0;   // first probe of the block being run
   auto launch = [&](int mode, int nprobes, int in, const T *rin, const T *pin, T *rout, T *pout,
                     int p0 = 0) -> hipError_t {
     TailArgs t = ta;
@@ -1272,6 +1299,8 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
     }
     a2.mode = mode;
     a2.nprobes = nprobes;
+    // the masks of random-sign probe j (class j) start at word j ny tiles_x
+    a2.rmask = rmask ? rmask + (size_t)(blk_first + p0) * (size_t)Q->shape[1] * (size_t)tiles_x : nullptr;
     a2.r_in = rin;
     a2.p_in = pin;
     a2.r_out = rout;
@@ -1290,6 +1319,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   double kernel_ms = 0.0;
   for (int first = 0; first < nprobes_total; first += block) {
     const int nb = std::min(block, nprobes_total - first);
+    blk_first = first;
     // state 0 <- initial; INIT: dots of v -> partials 0; FIRST: tail-init from
     // partials 0, state 0 -> 1, pass -> partials 1, vectors A; then STEP pairs
     // (state 1 -> 0, A -> B) and (state 0 -> 1, B -> A).  The final state is in 1.
@@ -1939,7 +1969,7 @@ static int tune_rows(Call &k) {
     if (lanes == 0) continue;
     for (int want : cands) {
       const int rows = pass2d_rows(sq, want);
-      if (want == LDQ_ROWS2D_TALL && k.o.precision != LDQ_MIXED) continue;
+      if (want == LDQ_ROWS2D_TALL && (k.o.precision != LDQ_MIXED || k.col.rad)) continue;
       if (want != LDQ_ROWS2D && want != LDQ_ROWS2D_TALL && rows >= pass2d_rows(sq, LDQ_ROWS2D)) continue;
       // the faster of two timing runs of each candidate
       double ms = 0.0;

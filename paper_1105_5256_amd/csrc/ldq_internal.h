@@ -124,6 +124,8 @@ struct Pass2D {
   const int32_t *colours;
   int rad;
   uint64_t seed;
+  const uint64_t *rmask;    // random signs for the specialised pass: the launch's
+                            // probes' strip masks in probe order (rad_masks)
   const double *uvec;       // or given probe vectors, probe-major [probe][n] (FP64)
   // operator
   double kappa2;            // constant shift (SQUARED and unfielded SHIFTED)

@@ -335,9 +335,10 @@ struct FastTile {
   const T *obs;        // observation planes (9 x n)
   const T *r_in, *p_in;
   T *r_out, *p_out;    // the probe's vectors
+  const uint64_t *rmask;   // random-sign probes: the probe's strip masks [ny][tiles_x]
 };
 
-template <typename T, int R, bool OBS, int NG, int TR, typename Prologue>
+template <typename T, int R, bool OBS, int NG, int TR, bool RAD, typename Prologue>
 __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prologue, double *q);
 
 // In the FP32 fast pass, workgroups 0 .. owner_blocks(nprobes) - 1 advance
@@ -354,8 +355,9 @@ __host__ __device__ inline int owner_blocks(int nprobes) { return sep_owner<T>()
 
 // FP32 without observations: held to 80 VGPRs, so that 6 waves per SIMD fit
 // the 41 x 144 tiles of a 512 x 512 launch at once (the owner branch, which
-// runs once per probe, may spill a few bytes for it).
-template <typename T, int R, bool OBS, int NG, int TR>
+// runs once per probe, may spill a few bytes for it).  RAD: random-sign
+// probes, whose entries come from a.rmask instead of the modular colouring.
+template <typename T, int R, bool OBS, int NG, int TR, bool RAD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !OBS ? 6 : 1))) void pass2d_fast(Pass2D<T> a) {
   constexpr int NQ = LDQ_NQ_BASE + NG;
   const int nown = owner_blocks<T>(a.nprobes);
@@ -385,11 +387,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   ft.p_in = a.p_in + off;
   ft.r_out = a.r_out + off;
   ft.p_out = a.p_out + off;
+  ft.rmask = RAD ? a.rmask + (size_t)probe * a.ny * a.tiles_x : nullptr;
   double q[NQ];
   auto prologue = [&]() {
     return pass_prologue<1>(a.tail, pref, tile, a.ntiles, MODE_STEP, sep_owner<T>() ? ROLE_TILE : ROLE_TILE0);
   };
-  if (!fast_tile<T, R, OBS, NG, TR>(ft, tile, prologue, q)) return;
+  if (!fast_tile<T, R, OBS, NG, TR, RAD>(ft, tile, prologue, q)) return;
   pass_epilogue_n<NQ>(pref, tile, a.ntiles, q);
 }
 
@@ -416,7 +419,9 @@ constexpr int rows_tall() {
 // requested before prologue() (the reduction of the previous launch's
 // partials, which yields alpha, beta and the probe's colour) so that its
 // memory round trips overlap; returns false when the probe is not active.
-template <typename T, int R, bool OBS, int NG, int TR, typename Prologue>
+// RAD: the probe's entries are the random signs of a.rmask (every site is the
+// probe's; the masks need a tile of at most 64 rows with its halo).
+template <typename T, int R, bool OBS, int NG, int TR, bool RAD, typename Prologue>
 __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prologue, double *q) {
   constexpr int H = R + 1;
   constexpr int W = 64 - 2 * H;
@@ -467,6 +472,20 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
     const unsigned so = (unsigned)min(max(ylo + u, 0), ny - 1) * rowb;
     qr0[u] = buf_ld((T *)nullptr, rs_rin, lx, so);
     qp0[u] = buf_ld((T *)nullptr, rs_pin, lx, so);
+  }
+  // Random signs: lane i holds the strip's mask of row ylo - 1 + i (the
+  // gradient row of step i): bit l is set when the probe's entry at column
+  // x0 - H + l is -1.  Masks are indexed by probe, not colour, so they are
+  // requested with the first rows, before the prologue.
+  unsigned mlo = 0u, mhi = 0u;
+  if constexpr (RAD) {
+    static_assert(TR + 2 * H <= 64, "one mask per lane and row of the march");
+    const int ym = ylo - 1 + lane;
+    if (lane < TR + 2 * H && ym >= 0 && ym < ny) {
+      const uint64_t m = a.rmask[(size_t)ym * a.tiles_x + tx];
+      mlo = (unsigned)m;
+      mhi = (unsigned)(m >> 32);
+    }
   }
   const Step step = prologue();
   if (!step.run) return false;
@@ -621,7 +640,13 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
           pr[u] = from_right(p_y);
         }
         // colour masks: row y - 1 now, row yd = y - R - 1 from R steps ago
-        const bool mine_g = cx == tg;
+        // (RAD: the sign masks, true where the probe's entry is -1)
+        bool mine_g = cx == tg;
+        if constexpr (RAD) {
+          const uint64_t m = ((uint64_t)(unsigned)__builtin_amdgcn_readlane((int)mhi, i) << 32) |
+                             (unsigned)__builtin_amdgcn_readlane((int)mlo, i);
+          mine_g = __builtin_amdgcn_inverse_ballot_w64(m);
+        }
         const bool mine_d = mg[(u + 5 - R) % 5];
         mg[u] = mine_g;
         tg -= astep;
@@ -643,7 +668,11 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
           // (kd I + L) p = t + (kd - kappa2) p on row y - 1 over the probe's
           // sites (scaled at the end)
           if (g_row) {
-            gacc0 += mine_g ? fma_t(dk_t, pq[(u + 4) % 5], tv) : T(0);
+            const T gv = fma_t(dk_t, pq[(u + 4) % 5], tv);
+            if constexpr (RAD)
+              gacc0 += mine_g ? -gv : gv;
+            else
+              gacc0 += mine_g ? gv : T(0);
             if constexpr (NG > 1 && OBS) gacc1 += mine_g ? ov : T(0);
           }
         }
@@ -677,7 +706,10 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
                        qv);
           g0 = fma_t(rd, rd, g0);
           g1 += qv;
-          racc += mine_d ? rd : T(0);
+          if constexpr (RAD)
+            racc += mine_d ? -rd : rd;
+          else
+            racc += mine_d ? rd : T(0);
         }
         // keep the scheduler from interleaving row steps (it would stretch
         // live ranges across the straight-line code)
@@ -750,7 +782,8 @@ __global__ __launch_bounds__(64) void batch2d_fast(Batch2D<T> b) {
   ft.p_out = b.p_out + off;
   double q[NQ];
   auto prologue = [&]() { return pass_prologue<1>(b.tail, pref, wk.tile, fd.ntiles, MODE_STEP); };
-  if (!fast_tile<T, R, false, NG, TR>(ft, wk.tile, prologue, q)) return;
+  ft.rmask = nullptr;
+  if (!fast_tile<T, R, false, NG, TR, false>(ft, wk.tile, prologue, q)) return;
   pass_epilogue_n<NQ>(pref, wk.tile, fd.ntiles, q);
 }
 
@@ -834,9 +867,17 @@ static void launch_gen(const Pass2D<T> &a, bool squared, bool obs, int nblocks, 
 template <typename T, int R, bool OBS, int TR>
 static void launch_fast_ng(const Pass2D<T> &a, int ng, hipStream_t stream) {
   const dim3 g(a.ntiles * a.nprobes + owner_blocks<T>(a.nprobes));
-  if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, R, OBS, 0, TR>), g, dim3(64), 0, stream, a);
-  else if (ng == 1 || !OBS) hipLaunchKernelGGL((pass2d_fast<T, R, OBS, 1, TR>), g, dim3(64), 0, stream, a);
-  else hipLaunchKernelGGL((pass2d_fast<T, R, OBS, OBS ? 2 : 1, TR>), g, dim3(64), 0, stream, a);
+  // random signs: without observations, standard tiles (launch_pass2d)
+  if constexpr (!OBS && TR == rows_full<R>()) {
+    if (a.rmask) {
+      if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, R, false, 0, TR, true>), g, dim3(64), 0, stream, a);
+      else hipLaunchKernelGGL((pass2d_fast<T, R, false, 1, TR, true>), g, dim3(64), 0, stream, a);
+      return;
+    }
+  }
+  if (ng == 0) hipLaunchKernelGGL((pass2d_fast<T, R, OBS, 0, TR, false>), g, dim3(64), 0, stream, a);
+  else if (ng == 1 || !OBS) hipLaunchKernelGGL((pass2d_fast<T, R, OBS, 1, TR, false>), g, dim3(64), 0, stream, a);
+  else hipLaunchKernelGGL((pass2d_fast<T, R, OBS, OBS ? 2 : 1, TR, false>), g, dim3(64), 0, stream, a);
 }
 
 template <typename T, int TR2, int TR1>
@@ -849,12 +890,15 @@ static void launch_fast(const Pass2D<T> &a, bool squared, bool obs, hipStream_t 
 
 // ngrad <= 2 (checked by the host driver for 2-D lattices); a.rows + 2H must
 // be a multiple of 5 (pass2d_rows).  The fast pass runs tiles of the standard
-// height, and in FP32 also of the tall height.
+// height, and in FP32 also of the tall height; with random signs (a.rmask),
+// standard tiles without observations only.
 template <typename T>
 hipError_t launch_pass2d(const Pass2D<T> &a, bool squared, bool obs, bool fast, hipStream_t stream) {
   const int nblocks = a.ntiles * a.nprobes;
   const bool std_rows = a.rows == (squared ? rows_full<2>() : rows_full<1>());
-  const bool tall_rows = sizeof(T) == 4 && a.rows == (squared ? rows_tall<2>() : rows_tall<1>());
+  const bool tall_rows =
+      sizeof(T) == 4 && !a.rmask && a.rows == (squared ? rows_tall<2>() : rows_tall<1>());
+  if (a.rmask && obs) fast = false;
   if (a.mode == MODE_STEP && fast && std_rows) {
     launch_fast<T, rows_full<2>(), rows_full<1>()>(a, squared, obs, stream);
   } else if (a.mode == MODE_STEP && fast && tall_rows) {
@@ -869,6 +913,35 @@ hipError_t launch_pass2d(const Pass2D<T> &a, bool squared, bool obs, bool fast, 
 
 template hipError_t launch_pass2d<float>(const Pass2D<float> &, bool, bool, bool, hipStream_t);
 template hipError_t launch_pass2d<double>(const Pass2D<double> &, bool, bool, bool, hipStream_t);
+
+// Sign masks of random-sign probes for the specialised pass: word
+// (j, y, tx) of out has bit l set when entry (x, y) of probe first + j is -1,
+// x = tx W - H + l the column of lane l in strip tx (0 outside the lattice).
+__global__ void rad_mask_kernel(uint64_t *out, uint64_t seed, int first, int nprobes, int nx, int ny, int tiles_x,
+                                int W, int H) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nprobes * ny * tiles_x) return;
+  const int tx = (int)(idx % tiles_x);
+  const int64_t jy = idx / tiles_x;
+  const int y = (int)(jy % ny), j = (int)(jy / ny);
+  uint64_t m = 0;
+  for (int l = 0; l < 64; ++l) {
+    const int x = tx * W - H + l;
+    if (x >= 0 && x < nx && rad_sign(seed, first + j, (int64_t)y * nx + x) < 0.0) m |= 1ull << l;
+  }
+  out[idx] = m;
+}
+
+hipError_t launch_rad_masks(uint64_t *out, uint64_t seed, int first, int nprobes, int nx, int ny, bool squared,
+                            hipStream_t stream) {
+  const int H = squared ? 3 : 2, W = 64 - 2 * H;
+  const int tiles_x = (nx + W - 1) / W;
+  const int64_t words = (int64_t)nprobes * ny * tiles_x;
+  if (words <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rad_mask_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, stream, out, seed, first,
+                     nprobes, nx, ny, tiles_x, W, H);
+  return hipGetLastError();
+}
 
 // Rows per wave tile near `want` with rows + 2H a multiple of 5 (halo H = R + 1).
 int pass2d_rows(bool squared, int want) {

@@ -77,6 +77,59 @@ def test_hutchinson_matches_oracle(ctx, shape, kind, precision, tol, bound):
         rel(info["std_error"], hu.standard_error(T)) < 1e-6
 
 
+@pytest.mark.parametrize("shape,kind,precision,with_grad", [
+    ((124, 80), ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, ldq.LDQ_MIXED, True),
+    ((124, 80), ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, ldq.LDQ_FP64, False),
+    ((126, 80), ldq.LDQ_SHIFTED_LAPLACIAN, ldq.LDQ_MIXED, False),
+    ((126, 80), ldq.LDQ_SHIFTED_LAPLACIAN, ldq.LDQ_FP64, True)])
+def test_hutchinson_specialised_pass(ctx, shape, kind, precision, with_grad):
+    """Random signs in the specialised 2-D pass (per-row sign masks of the
+    strips; standard tiles) on lattices with interior, boundary and ragged
+    tiles, in two probe blocks of two lanes each (masks offset by block and
+    lane): against the oracle and against the general pass (short tiles)."""
+    s, seed, k2 = 7, 0xC0FFEE, 0.3
+    say(f"hutchinson specialised pass {shape} kind={kind} precision={precision} grad={with_grad}")
+    n = int(np.prod(shape))
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, kind, k2))
+    M = lattice.shifted_laplacian(shape, k2)
+    if kind == ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN:
+        Qo, kd, sc = lattice.squared(M), k2, 2.0
+    else:
+        Qo, kd, sc = M, 1.3, 0.5
+    dQ = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, kd, scale=sc))
+    dQo = sc * lattice.shifted_laplacian(shape, kd)
+    tol = 1e-5 if precision == ldq.LDQ_MIXED else 1e-10
+    bound = 1e-4 if precision == ldq.LDQ_MIXED else 1e-8
+    # standard tiles (specialised pass) and short ones (general pass): rows
+    # plus twice the halo is a multiple of five
+    std_rows, gen_rows = (34, 9) if kind == ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN else (36, 11)
+
+    def run(rows):
+        o = hopts(s, seed, tol=tol, grad_tol=tol, precision=precision, tile_rows=rows, lanes=2, probe_block=4)
+        if with_grad:
+            v, g, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], o)
+        else:
+            (v, info), g = ldq.ldq_logdet(ctx.handle, Q, o), None
+        assert info["tile_rows"] == rows
+        return v, g, ldq.ldq_probe_terms(ctx.handle), info
+
+    v, g, terms, info = run(std_rows)
+    vg, gg, terms_g, _ = run(gen_rows)
+    V = hu.rademacher(n, s, seed)
+    sig, coef = shifts.log_shifts(info["lambda_min"], info["lambda_max"], 20)
+    H, T = hu.hutchinson_rational(Qo, V, sig, coef)
+    print(f"logdet {v:.10g} general pass {vg:.10g} oracle {H:.10g}: rel {rel(v, H):.1e} / {rel(vg, H):.1e}; "
+          f"max term rel {np.max(np.abs(terms[:, 0] - T) / np.abs(T)):.1e}; iters {info['iters_max']}")
+    assert terms.shape[0] == s
+    assert np.allclose(terms[:, 0], T, rtol=bound, atol=0) and np.allclose(terms_g[:, 0], T, rtol=bound, atol=0)
+    assert rel(v, H) < bound and rel(vg, H) < bound
+    assert np.allclose(terms[:, 0], terms_g[:, 0], rtol=bound, atol=0)
+    if with_grad:
+        G, _ = hu.hutchinson_grad(Qo, [dQo], V)
+        print(f"grad {g[0]:.10g} general pass {gg[0]:.10g} oracle {G[0]:.10g}")
+        assert rel(g[0], G[0]) < 10 * bound and rel(gg[0], G[0]) < 10 * bound
+
+
 def test_hutchinson_seed_changes_probes_and_estimate_covers_exact(ctx):
     shape = (64, 64)
     say(f"hutchinson statistics {shape}")
