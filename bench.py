@@ -110,7 +110,8 @@ class Workload:
             self.extra = dict(colouring=L.LDQ_COLOUR_RADEMACHER, nrandom=41, seed=0x5EED)
             self.describe = ("hutch512: 2-D 512x512 lattice, Q = (0.05 I + L)^2 (13-point), Hutchinson's estimator "
                              "with 41 random-sign probes (SplitMix64, seed 0x5EED), N=20 shifts, log det + d/dkappa2")
-            self.kernel = "pass2d_kernel<float, R=2, 1 gradient> (general 2-D pass, random-sign probes)"
+            self.kernel = ("pass2d_fast<float, R=2, no observations, 1 gradient, random signs> "
+                           "(fused 2-D pass, per-row sign masks)")
             self.n = 512 * 512
         elif name == "lattice64_5pt":
             wl = workloads.lattice2d_5pt(64, 0.1, 2)
