@@ -358,7 +358,7 @@ __host__ __device__ inline int owner_blocks(int nprobes) { return sep_owner<T>()
 // runs once per probe, may spill a few bytes for it).  RAD: random-sign
 // probes, whose entries come from a.rmask instead of the modular colouring.
 template <typename T, int R, bool OBS, int NG, int TR, bool RAD>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !OBS ? 6 : 1))) void pass2d_fast(Pass2D<T> a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !OBS && TR < LDQ_ROWS2D_TALL ? 6 : 1))) void pass2d_fast(Pass2D<T> a) {
   constexpr int NQ = LDQ_NQ_BASE + NG;
   const int nown = owner_blocks<T>(a.nprobes);
   if ((int)blockIdx.x < nown) {
@@ -413,6 +413,16 @@ constexpr int rows_tall() {
   while ((r + 2 * R + 2) % 5 != 0) ++r;
   return r;
 }
+// Rows of r and p requested ahead of the march: one five-row ring, or two for
+// the tall tile (its waves are half as many, so registers allow the deeper
+// prefetch, which halves the dependent round trips of a wave's 70 rows).
+#ifndef LDQ_PF_TALL
+#define LDQ_PF_TALL 10
+#endif
+template <int R, int TR>
+constexpr int prefetch_rows() {
+  return TR == rows_tall<R>() ? LDQ_PF_TALL : 5;
+}
 
 // One tile of one probe: the march of the fused pass; q[] receives this
 // wave's sums of the pass's dot products.  The first rows of r and p are
@@ -465,10 +475,13 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
   const unsigned lst = xout ? lx : 0xFFFFFFF0u;
   const unsigned rowb = (unsigned)nx * (unsigned)sizeof(T);         // row stride in bytes
 
-  // rows ylo .. ylo + 4 (clamped into the lattice), requested now
-  T qr0[5], qp0[5];
+  // rows ylo .. ylo + PF - 1 (clamped into the lattice), requested now
+  constexpr int PF = prefetch_rows<R, TR>();
+  static_assert(PF == 5 || PF == 10, "the prefetch ring is one or two stencil rings");
+  static_assert((TR + 2 * H) % PF == 0, "the march is whole prefetch rings");
+  T qr0[PF], qp0[PF];
 #pragma unroll
-  for (int u = 0; u < 5; ++u) {
+  for (int u = 0; u < PF; ++u) {
     const unsigned so = (unsigned)min(max(ylo + u, 0), ny - 1) * rowb;
     qr0[u] = buf_ld((T *)nullptr, rs_rin, lx, so);
     qp0[u] = buf_ld((T *)nullptr, rs_pin, lx, so);
@@ -523,8 +536,8 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
     // code it would otherwise compute them all up front and run out of
     // scalar registers.
     unsigned yo = IN ? (unsigned)ylo * rowb : 0u;
-    const unsigned rowb5 = 5u * rowb, rowbR = (unsigned)R * rowb;
-    T qr[5], qp[5];
+    const unsigned rowbPF = (unsigned)PF * rowb, rowbR = (unsigned)R * rowb;
+    T qr[PF], qp[PF];
     auto fetch = [&](int slot, int i) {
       const int yy = ylo + min(i, NFULL - 1);
       const int yc = IN ? yy : min(max(yy, 0), ny - 1);
@@ -532,7 +545,7 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
       qp[slot] = buf_ld((T *)nullptr, rs_pin, lx, (unsigned)yc * rowb);
     };
 #pragma unroll
-    for (int u = 0; u < 5; ++u) {
+    for (int u = 0; u < PF; ++u) {
       qr[u] = qr0[u];
       qp[u] = qp0[u];
     }
@@ -603,8 +616,9 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
     // it to wait for them), and every row test below is a compile-time
     // constant.  Boundary tiles keep the loop and run-time row tests:
     // unrolled, their masking exhausts the registers.
-    // five row steps starting at step i0 (ring slots are compile-time)
-    auto group = [&](int i0) {
+    // five row steps starting at step i0 (ring slots are compile-time; the
+    // rows arriving are in prefetch slots sb .. sb + 4)
+    auto group = [&](int i0, int sb) {
 #pragma unroll
       for (int u = 0; u < 5; ++u) {
         const int i = i0 + u;
@@ -616,8 +630,8 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
         const bool s_row = IN ? (i >= H + R && i < H + R + RF) : (y - R >= y0 && y - R < yb);
         const bool d_row = IN ? (i >= H + R + 1 && i < H + R + 1 + RF) : (y - R - 1 >= y0 && y - R - 1 < yb);
         // ---- row y arrives: p_k = r_k + beta p_{k-1}
-        T r_y = qr[u];
-        T p_y = fma_t(beta_t, qp[u], qr[u]);
+        T r_y = qr[sb + u];
+        T p_y = fma_t(beta_t, qp[sb + u], qr[sb + u]);
         if constexpr (!IN) {
           const bool in = xin && y >= 0 && y < ny;
           r_y = in ? r_y : T(0);
@@ -625,13 +639,13 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
         }
         if constexpr (IN) {
           __asm__ volatile("" : "+s"(yo), "+s"(tg));
-          // the last five steps prefetch nothing (no rows follow)
-          if (i + 5 < NFULL) {
-            qr[u] = buf_ld((T *)nullptr, rs_rin, lx, yo + rowb5);
-            qp[u] = buf_ld((T *)nullptr, rs_pin, lx, yo + rowb5);
+          // the last PF steps prefetch nothing (no rows follow)
+          if (i + PF < NFULL) {
+            qr[sb + u] = buf_ld((T *)nullptr, rs_rin, lx, yo + rowbPF);
+            qp[sb + u] = buf_ld((T *)nullptr, rs_pin, lx, yo + rowbPF);
           }
         } else {
-          fetch(u, i + 5);
+          fetch(sb + u, i + PF);
         }
         rq[u] = r_y;
         pq[u] = p_y;
@@ -728,10 +742,13 @@ __device__ inline bool fast_tile(const FastTile<T> &a, int tile, Prologue prolog
     };
     if constexpr (IN) {
 #pragma unroll
-      for (int i0 = 0; i0 < NFULL; i0 += 5) group(i0);
+      for (int i0 = 0; i0 < NFULL; i0 += 5) group(i0, i0 % PF);
     } else {
 #pragma nounroll
-      for (int i0 = 0; i0 < nrows; i0 += 5) group(i0);
+      for (int i0 = 0; i0 < nrows; i0 += PF) {
+        group(i0, 0);
+        if constexpr (PF == 10) group(i0 + 5, 5);
+      }
     }
     q[2] = (double)racc;
     if constexpr (NG > 0) q[LDQ_NQ_BASE] = gs0 * (double)gacc0;
