@@ -279,6 +279,21 @@ int ldq_probe_terms(ldq_ctx *ctx, double *out, int64_t capacity, int64_t *count,
 int ldq_logm_apply(ldq_ctx *ctx, const ldq_op *Q, int nvec, const double *V, double *Y, const ldq_options *opts,
                    ldq_info *info /* nullable */);
 
+/* X = Q^{-1} B for nvec right-hand sides: the base system of the same Krylov
+ * iteration (Sec. 2.1: the CG whose coefficients drive every shift), e.g. the
+ * posterior mean Q_p^{-1} tau A^T y of the Gauss-linear model (Sec. 2,
+ * eq. (3)).  Each system runs until ||r|| <= grad_tol ||b|| (tol when
+ * grad_tol <= 0); the solutions are not kept as iterates but formed as
+ * x = sum_m S_m r_m, S_m = alpha_m + beta_m S_{m+1}, from a first solve's
+ * coefficients and accumulated by a second, identical solve.  B and X are
+ * DEVICE arrays of nvec x n doubles, vector j at [j * n] (owned by the
+ * caller; X is overwritten, B is not).  Lattice operators (with or without
+ * the observation term); at most 8192 iterations per vector
+ * (LDQ_E_UNSUPPORTED beyond); LDQ_E_NOT_SPD if a p^T Q p is not positive.
+ * info describes the first solve. */
+int ldq_solve(ldq_ctx *ctx, const ldq_op *Q, int nvec, const double *B, double *X, const ldq_options *opts,
+              ldq_info *info /* nullable */);
+
 /* Many independent fields (e.g. one operator per field); per field f:
  * logdet[f], grad[f * nparams + i] (dQ[f * nparams + i]), info[f] (nullable). */
 int ldq_logdet_batched(ldq_ctx *ctx, int nfields, const ldq_op *const *Q, int nparams,

@@ -893,6 +893,7 @@ struct Call {
   int stats[8];
   int rows2d;        // 2-D lattices: rows per wave tile (0: the specialised pass's standard tile)
   int lanes;         // lattices: concurrent chains of pass launches per probe block (1..LDQ_MAX_LANES)
+  bool force_base;   // the base system must converge even without derivatives (Q^{-1} v)
   // materialising f_N(Q) v (second solve): y_j = sum_m w[j][m] r_m of probe j,
   // accumulated over `mat_steps` iterations (lattice operators, one block)
   const double *mat_w;
@@ -1170,7 +1171,7 @@ static int run_krylov(Call &k, ldq_info *info, double *out_sums) {
   ta.grad_tol2 = gt * gt;
   ta.max_iter = k.o.max_iter;
   ta.active_count = active_count;
-  ta.need_base = P > 0;
+  ta.need_base = P > 0 || k.force_base;
   const int hcap = hist_cap(block, k.o.max_iter);
   CHK(c->hist.reserve((size_t)block * hcap * 2 * sizeof(double)));
   ta.hist = c->hist.as<double>();
@@ -2173,10 +2174,26 @@ static void mat_weights(const double *h, int K, double vnorm2, double tol2, cons
   }
 }
 
-extern "C" int ldq_logm_apply(ldq_ctx *c, const ldq_op *Q, int nvec, const double *V, double *Y,
-                              const ldq_options *opts, ldq_info *info) {
+// The base system alone (sigma = 0: zeta = 1, alpha^s = alpha, beta^s = beta):
+// Q^{-1} v = x_K = sum_{m < K} S_m r_m with S_m = alpha_m + beta_m S_{m+1},
+// S_K = 0, over every iteration the probe ran (the base system met its
+// tolerance by then: the solve forces it).
+static void base_weights(const double *h, int K, double *w) {
+  double S = 0.0;
+  for (int m = K - 1; m >= 0; --m) {
+    S = h[2 * m] + (m + 1 < K ? h[2 * (m + 1) + 1] * S : 0.0);
+    w[m] = S;
+  }
+}
+
+// Y = f_N(Q) V (inverse = false) or Q^{-1} V (inverse = true) by two
+// identical solves: the first records the base coefficients, the host forms
+// the residual weights, the second accumulates Y.
+static int materialise(ldq_ctx *c, const ldq_op *Q, int nvec, const double *V, double *Y, const ldq_options *opts,
+                       ldq_info *info, bool inverse) {
   if (!c || !Q || nvec < 1 || !V || !Y) return fail(LDQ_E_INVALID, "invalid arguments");
-  if (Q->kind != OPK_LATTICE) return fail(LDQ_E_UNSUPPORTED, "f_N(Q) v is implemented for lattice operators");
+  if (Q->kind != OPK_LATTICE)
+    return fail(LDQ_E_UNSUPPORTED, "%s is implemented for lattice operators", inverse ? "Q^-1 v" : "f_N(Q) v");
   CHK(set_device(c));
   // V and Y are read and written by kernels: device (or managed) memory only
   for (const void *ptr : {(const void *)V, (const void *)Y}) {
@@ -2201,6 +2218,7 @@ extern "C" int ldq_logm_apply(ldq_ctx *c, const ldq_op *Q, int nvec, const doubl
   CHK(prepare_call(k, c, Q, 0, nullptr, &o));
   k.col.rad = false;
   k.col.uvec = V;
+  k.force_base = inverse;
   CHK(tune_rows(k));
   k.lanes = 1;
   double sums[1 + LDQ_MAXP] = {};
@@ -2222,9 +2240,13 @@ extern "C" int ldq_logm_apply(ldq_ctx *c, const ldq_op *Q, int nvec, const doubl
   if (kmax > hcap) return fail(LDQ_E_UNSUPPORTED, "%d iterations exceed the %d the coefficient history holds", kmax, hcap);
   const int ws = kmax + 1;
   std::vector<double> w((size_t)nvec * ws, 0.0);
-  for (int j = 0; j < nvec; ++j)
-    mat_weights(hist.data() + (size_t)j * hcap * 2, pst[j].iter, pst[j].vnorm2, k.o.tol * k.o.tol, sh.data(),
-                sh.data() + LDQ_MAXN, k.o.nshifts, w.data() + (size_t)j * ws);
+  for (int j = 0; j < nvec; ++j) {
+    if (inverse)
+      base_weights(hist.data() + (size_t)j * hcap * 2, pst[j].iter, w.data() + (size_t)j * ws);
+    else
+      mat_weights(hist.data() + (size_t)j * hcap * 2, pst[j].iter, pst[j].vnorm2, k.o.tol * k.o.tol, sh.data(),
+                  sh.data() + LDQ_MAXN, k.o.nshifts, w.data() + (size_t)j * ws);
+  }
   CHK(c->matw.reserve(w.size() * sizeof(double)));
   HIPCHK(hipMemcpyAsync(c->matw.ptr, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   // the second, identical solve accumulates y
@@ -2238,6 +2260,16 @@ extern "C" int ldq_logm_apply(ldq_ctx *c, const ldq_op *Q, int nvec, const doubl
   HIPCHK(hipStreamSynchronize(c->stream));
   if (info) *info = first;
   return LDQ_OK;
+}
+
+extern "C" int ldq_logm_apply(ldq_ctx *c, const ldq_op *Q, int nvec, const double *V, double *Y,
+                              const ldq_options *opts, ldq_info *info) {
+  return materialise(c, Q, nvec, V, Y, opts, info, false);
+}
+
+extern "C" int ldq_solve(ldq_ctx *c, const ldq_op *Q, int nvec, const double *B, double *X, const ldq_options *opts,
+                         ldq_info *info) {
+  return materialise(c, Q, nvec, B, X, opts, info, true);
 }
 
 extern "C" int ldq_probe_terms(ldq_ctx *c, double *out, int64_t capacity, int64_t *count, int *nparams) {

@@ -108,6 +108,7 @@ _SIGNATURES = {
     "ldq_probe_terms": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_int)]),
     "ldq_logm_apply": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P]),
+    "ldq_solve": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P]),
     "ldq_logdet_batched": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int, _P, ctypes.POINTER(ldq_options),
                                           _P, _P, _P]),
 }
@@ -320,6 +321,22 @@ def ldq_logm_apply(ctx, Q, V, opts=None):
     _check(load().ldq_logm_apply(ctx, Q, V.shape[0], ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
                                  ctypes.byref(opts), ctypes.byref(info)), "ldq_logm_apply")
     return Y, info.as_dict()
+
+
+def ldq_solve(ctx, Q, B, opts=None):
+    """Q^{-1} B for the rows of B (a torch float64 CUDA tensor, nvec x n, contiguous):
+    returns (X of the same shape on the same device, info dict of the first solve)."""
+    import torch
+    if B.dim() == 1:
+        B = B[None]
+    if B.dtype != torch.float64 or not B.is_cuda or not B.is_contiguous():
+        raise ValueError("B must be a contiguous float64 CUDA tensor")
+    X = torch.empty_like(B)
+    opts = opts if opts is not None else ldq_options_default()
+    info = ldq_info()
+    _check(load().ldq_solve(ctx, Q, B.shape[0], ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+                            ctypes.byref(opts), ctypes.byref(info)), "ldq_solve")
+    return X, info.as_dict()
 
 
 def ldq_logdet_batched(ctx, Qs, dQs=None, opts=None):

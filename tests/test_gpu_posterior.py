@@ -1,0 +1,111 @@
+"""GPU parity of the solve Q^{-1} B (ldq_solve) and of the Gauss-linear
+objective built on it (Sec. 1, eq. (1)-(3): posterior mean, -2 log p(y) and
+its gradient, the fit) against the oracle.  Bounds: FP64 solves at tol 1e-12
+are within cond(Q) * tol of the direct solve (1e-8 relative here); the mixed
+form (FP32 vectors) within 1e-4.  With identity probing the log dets and
+traces are exact up to the quadrature, so the objective matches the oracle's
+exact value to 1e-8 relative and its gradient the oracle's central
+differences to 1e-5."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lattice, posterior
+from paper_1105_5256_amd import fit, ldq, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ldq.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("shape,kind,obs,precision,tol,bound", [
+    ((31, 27), ldq.LDQ_SHIFTED_LAPLACIAN, False, ldq.LDQ_FP64, 1e-12, 1e-8),
+    ((30, 26), ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, True, ldq.LDQ_FP64, 1e-12, 1e-8),
+    ((10, 9, 8), ldq.LDQ_SHIFTED_LAPLACIAN, False, ldq.LDQ_FP64, 1e-12, 1e-8),
+    ((130, 90), ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, False, ldq.LDQ_MIXED, 1e-6, 1e-4)])
+def test_solve_matches_oracle(ctx, shape, kind, obs, precision, tol, bound):
+    import torch
+    say(f"solve {shape} kind={kind} obs={obs} precision={precision}")
+    n = int(np.prod(shape))
+    k2 = 1.0
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, kind, k2, scale=1.5))
+    Qo = lattice.shifted_laplacian(shape, k2)
+    Qo = 1.5 * (lattice.squared(Qo) if kind == ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN else Qo)
+    if obs:
+        corner, weight = workloads.observations(shape, 150, 7)
+        ldq.ldq_op_add_obs(Q, corner, weight, 3.0)
+        Qo = lattice.posterior_precision(Qo, corner, weight, 3.0)
+    B = np.random.default_rng(11).standard_normal((3, n))
+    Bt = torch.as_tensor(B, device="cuda")
+    X, info = ldq.ldq_solve(ctx.handle, Q, Bt, ldq.ldq_options_default(tol=tol, grad_tol=tol, precision=precision))
+    X = X.cpu().numpy()
+    Xo = posterior.solve(Qo, B.T).T
+    err = np.linalg.norm(X - Xo, axis=1) / np.linalg.norm(Xo, axis=1)
+    res = np.linalg.norm((Qo @ X.T).T - B, axis=1) / np.linalg.norm(B, axis=1)
+    print(f"rel err {err.max():.1e}, rel residual {res.max():.1e}, iters {info['iters_max']}")
+    assert np.all(err < bound)
+    assert np.array_equal(Bt.cpu().numpy(), B)   # B is not modified
+
+
+def noisy_case(shape=(16, 14), nobs=500, theta=(np.log(0.5), np.log(1.3), np.log(25.0)), seed=9):
+    """Data y = A x + e drawn from the model at theta (exact field draw); more
+    observations than sites, so that the maximiser is interior (near theta)."""
+    kappa2, taux, tauy = np.exp(theta)
+    n = int(np.prod(shape))
+    x = workloads.spde_field_sample(shape, kappa2, taux, seed)
+    corner, weight = workloads.observations(shape, nobs, seed + 1)
+    A = lattice.observation_matrix(n, corner, weight)
+    y = A @ x + np.random.default_rng(seed + 2).standard_normal(nobs) / np.sqrt(tauy)
+    return n, corner, weight, A, y
+
+
+def oracle_F(shape, A, y, theta):
+    kappa2, taux, tauy = np.exp(theta)
+    Qx = taux * taux * lattice.squared(lattice.shifted_laplacian(shape, kappa2))
+    return posterior.neg2_loglik(Qx, A, y, tauy)
+
+
+def test_noisy_objective_and_gradient_match_oracle(ctx):
+    shape = (16, 14)
+    say(f"noisy objective {shape}")
+    n, corner, weight, A, y = noisy_case(shape)
+    data = fit.noisy_data(y, corner, weight, shape)
+    opts = ldq.ldq_options_default(colouring=ldq.LDQ_COLOUR_IDENTITY, tol=1e-12, grad_tol=1e-12, nshifts=40)
+    for theta in [np.array([np.log(0.5), np.log(1.3), np.log(25.0)]), np.array([0.3, -0.2, 2.5])]:
+        F, dF, _ = fit.objective_noisy(ctx, data, shape, theta, opts)
+        Fo = oracle_F(shape, A, y, theta)
+        h = 1e-4
+        dFo = np.array([(oracle_F(shape, A, y, theta + h * e) - oracle_F(shape, A, y, theta - h * e)) / (2 * h)
+                        for e in np.eye(3)])
+        print(f"theta {theta}: F {F:.10g} oracle {Fo:.10g}; dF {dF} oracle FD {dFo}")
+        assert abs(F - Fo) <= 1e-8 * abs(Fo)
+        assert np.all(np.abs(dF - dFo) <= 1e-5 * np.abs(dFo).max())
+
+
+def test_fit_noisy_reaches_oracle_minimiser(ctx):
+    from scipy.optimize import minimize
+    shape = (16, 14)
+    say(f"noisy fit {shape}")
+    n, corner, weight, A, y = noisy_case(shape)
+    theta0 = np.zeros(3)
+    r = fit.fit_noisy(ctx, y, corner, weight, shape, k=1, theta0=theta0, colouring=ldq.LDQ_COLOUR_IDENTITY,
+                      tol=1e-12, gtol=1e-9)
+    ro = minimize(lambda t: oracle_F(shape, A, y, t), theta0, method="Nelder-Mead",
+                  options={"xatol": 1e-7, "fatol": 1e-10, "maxiter": 4000})
+    print(f"fit {r['theta']} F {r['f']:.10g} ({r['evals']} evals); oracle {ro.x} F {ro.fun:.10g}")
+    assert r["success"]
+    assert np.allclose(r["theta"], ro.x, atol=1e-4)
