@@ -109,3 +109,32 @@ def test_fit_noisy_reaches_oracle_minimiser(ctx):
     print(f"fit {r['theta']} F {r['f']:.10g} ({r['evals']} evals); oracle {ro.x} F {ro.fun:.10g}")
     assert r["success"]
     assert np.allclose(r["theta"], ro.x, atol=1e-4)
+
+
+def test_solve_error_paths(ctx):
+    import ctypes
+    import torch
+    say("solve error paths")
+    rp = np.arange(5, dtype=np.int32)
+    ci = np.arange(4, dtype=np.int32)
+    C = ctx.op(ldq.ldq_op_csr(ctx.handle, 4, rp, ci, np.full(4, 2.0)))
+    with pytest.raises(ldq.LdqError) as e:
+        ldq.ldq_solve(ctx.handle, C, torch.ones(1, 4, dtype=torch.float64, device="cuda"))
+    assert e.value.status == ldq.LDQ_E_UNSUPPORTED
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, (6, 5), ldq.LDQ_SHIFTED_LAPLACIAN, 0.5))
+    opts = ldq.ldq_options_default()
+    lib = ldq.load()
+    # host memory is refused (the kernels could not read it), as are an empty
+    # set of right-hand sides and NULL arrays
+    host, out = np.ones(30), np.zeros(30)
+    hp, op_ = host.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p)
+    assert lib.ldq_solve(ctx.handle, Q, 1, hp, op_, ctypes.byref(opts), None) == ldq.LDQ_E_INVALID
+    B = torch.ones(1, 30, dtype=torch.float64, device="cuda")
+    X = torch.zeros_like(B)
+    bp, xp = ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(X.data_ptr())
+    assert lib.ldq_solve(ctx.handle, Q, 0, bp, xp, ctypes.byref(opts), None) == ldq.LDQ_E_INVALID
+    assert lib.ldq_solve(ctx.handle, Q, 1, None, xp, ctypes.byref(opts), None) == ldq.LDQ_E_INVALID
+    # a solve after the refused calls still works: Q x = 1 on the lattice
+    Xs, _ = ldq.ldq_solve(ctx.handle, Q, B, ldq.ldq_options_default(tol=1e-12, grad_tol=1e-12))
+    Qo = lattice.shifted_laplacian((6, 5), 0.5)
+    assert np.linalg.norm(Qo @ Xs.cpu().numpy()[0] - 1.0) < 1e-10 * np.sqrt(30)
