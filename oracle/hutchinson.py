@@ -26,8 +26,11 @@ z ^= z >> 27, z *= 0x94D049BB133111EB, z ^= z >> 31 (all modulo 2**64).  Sites a
 numbered x + nx * (y + ny * z) on lattices and by row on CSR matrices.
 """
 import numpy as np
+import scipy.fft as sfft
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
+
+from . import exact
 
 GAMMA = np.uint64(0x9E3779B97F4A7C15)
 MIX1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -97,3 +100,27 @@ def hoeffding_halfwidth(n, lmin, lmax, s, delta):
     term v^T log(Q) v lies in [n log lmin, n log lmax] (||v||^2 = n), so
     t = n (log lmax - log lmin) sqrt(log(2 / delta) / (2 s))."""
     return float(n * (np.log(lmax) - np.log(lmin)) * np.sqrt(np.log(2.0 / delta) / (2.0 * s)))
+
+
+def hutchinson_dst(shape, kappa2, V, power=1, dQs=()):
+    """Exact per-probe terms for Q = (kappa2 I + L)^power on a Dirichlet
+    lattice with constant kappa2 (large lattices): Q = S diag(mu) S with the
+    orthonormal DST-I S, so v^T log(Q) v = sum_f log(mu_f) (S v)_f^2 and
+    Q^{-1} v = S diag(1/mu) S v.  Returns (H, terms [s], g, gradient terms
+    [s, len(dQs)]) with (Q^{-1} v_j)^T dQ_i v_j."""
+    shape = tuple(int(m) for m in shape)
+    rshape = tuple(reversed(shape))
+    mu = (kappa2 + exact.lattice_eigenvalues(shape)) ** power
+    logmu = np.log(mu)
+    V = np.asarray(V, dtype=np.float64)
+    terms = np.empty(V.shape[1])
+    gterms = np.zeros((V.shape[1], len(dQs)))
+    for j in range(V.shape[1]):
+        v = V[:, j]
+        sv = sfft.dstn(v.reshape(rshape), type=1, norm="ortho")
+        terms[j] = np.sum(logmu * sv * sv)
+        if dQs:
+            x = sfft.idstn(sv / mu, type=1, norm="ortho").ravel()
+            for i, dQ in enumerate(dQs):
+                gterms[j, i] = x @ (dQ @ v)
+    return float(np.mean(terms)), terms, gterms.mean(axis=0), gterms

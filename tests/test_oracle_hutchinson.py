@@ -7,6 +7,7 @@ import itertools
 import os
 
 import numpy as np
+import pytest
 import scipy.sparse as sp
 
 from oracle import hutchinson as hu
@@ -101,3 +102,20 @@ def test_hoeffding_halfwidth_covers():
     for seed in range(20):
         H, _ = hu.hutchinson_exact(Q, hu.rademacher(Q.shape[0], s, seed))
         assert abs(H - tr) <= t
+
+
+@pytest.mark.parametrize("power", [1, 2])
+def test_dst_route_matches_eigh(power):
+    """The DST route for large lattices against the dense eigendecomposition
+    (terms) and sparse solves (gradient terms) on a small lattice."""
+    shape, k2 = (9, 7), 0.3
+    n = 63
+    M = lattice.shifted_laplacian(shape, k2)
+    Q = lattice.squared(M) if power == 2 else M
+    V = hu.rademacher(n, 5, 77)
+    dQ = 2 * M
+    H, T, g, G = hu.hutchinson_dst(shape, k2, V, power, [dQ])
+    He, Te = hu.hutchinson_exact(Q, V)
+    ge, Ge = hu.hutchinson_grad(Q, [dQ], V)
+    assert np.allclose(T, Te, rtol=1e-11, atol=0) and abs(H - He) <= 1e-11 * abs(He)
+    assert np.allclose(G[:, 0], Ge[:, 0], rtol=1e-10, atol=0) and abs(g[0] - ge[0]) <= 1e-10 * abs(ge[0])
