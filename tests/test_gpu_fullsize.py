@@ -110,3 +110,30 @@ def test_field128_constant_full_size(ctx):
     print(f"logdet rel {rel(val, E):.2e}, grad rel {rel(grad[0], G[0]):.2e}, iters {info['iters_max']}")
     assert info["ncolours"] == 70 and info["enclosure_violations"] == 0
     assert rel(val, E) < 1e-6 and rel(grad[0], G[0]) < 1e-4
+
+
+def test_hutch512_full_size(ctx):
+    """Random-sign probes at the benchmark's size and launch configuration
+    (specialised pass with per-row sign masks, two lanes, 34-row tiles):
+    every probe term, the mean and the gradient against the oracle's exact
+    values (DST-I diagonalisation), on 8 of the benchmark's 41 probes."""
+    from oracle import hutchinson as hu
+    wl = workloads.lattice2d_sq(512)
+    shape, kappa2 = wl["shape"], wl["kappa2"]
+    s, seed = 8, 0x5EED
+    say(f"full size {shape} 13-point, {s} random-sign probes, mixed, tol 1e-4")
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, kappa2))
+    dQ = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, kappa2, scale=2.0))
+    opts = ldq.ldq_options_default(nshifts=20, tol=1e-4, grad_tol=1e-4, precision=ldq.LDQ_MIXED,
+                                   colouring=ldq.LDQ_COLOUR_RADEMACHER, nrandom=s, seed=seed, lanes=2, tile_rows=34)
+    val, grad, info = ldq.ldq_logdet_grad(ctx.handle, Q, [dQ], opts)
+    terms = ldq.ldq_probe_terms(ctx.handle)
+    n = shape[0] * shape[1]
+    V = hu.rademacher(n, s, seed)
+    H, T, g, _ = hu.hutchinson_dst(shape, kappa2, V, 2, [2 * lattice.shifted_laplacian(shape, kappa2)])
+    print(f"logdet rel {rel(val, H):.2e}, grad rel {rel(grad[0], g[0]):.2e}, iters {info['iters_max']}, "
+          f"max term rel {np.max(np.abs(terms[:, 0] - T) / np.abs(T)):.2e}, tile rows {info['tile_rows']}, "
+          f"lanes {info['lanes']}")
+    assert info["tile_rows"] == 34 and info["lanes"] == 2 and info["enclosure_violations"] == 0
+    assert rel(val, H) < 1e-6 and rel(grad[0], g[0]) < 1e-5
+    assert np.allclose(terms[:, 0], T, rtol=1e-5)
