@@ -68,7 +68,7 @@ template <typename S>
 hipError_t launch_mat_accum_shifts(const S *x, const cplx *c, int cstride, int m, int N, int nb, int64_t n, cplx *z,
                                    bool init, hipStream_t s);
 hipError_t launch_lattice_bilinear(const cplx *z, int nv, int nx, int ny, int nz, bool diag, double scale, double kd,
-                                   const double *field, cplx *out, hipStream_t s);
+                                   const double *field, const double *planes, cplx *out, hipStream_t s);
 hipError_t launch_batch_compact(const FieldDesc *, const int32_t *, int, const ProbeState *, ProbeState *, WorkItem *,
                                 int *, hipStream_t);
 }  // namespace ldq
@@ -2044,10 +2044,12 @@ static int consistent_gradient(Call &k, double *grad) {
   std::vector<cplx> q((size_t)nb * N);
   for (int i = 0; i < k.nparams; ++i) {
     const ldq_op *d = k.dQ[i];
-    const bool diag = d->kind == OPK_DIAG;
+    const bool diag = d->kind == OPK_DIAG, gram = d->kind == OPK_OBSGRAM;
+    // scales as the passes apply them (an observation gram carries its weight in tau)
     HIPCHK(launch_lattice_bilinear(c->matz.as<cplx>(), nb * N, (int)Q->shape[0], (int)Q->shape[1],
-                                   Q->ndim == 3 ? (int)Q->shape[2] : 1, diag, d->scale, diag ? 0.0 : d->kappa2,
-                                   d->field, c->matq.as<cplx>(), c->stream));
+                                   Q->ndim == 3 ? (int)Q->shape[2] : 1, diag, gram ? d->tau : d->scale,
+                                   diag || gram ? 0.0 : d->kappa2, gram ? nullptr : d->field,
+                                   gram ? d->obs9 : nullptr, c->matq.as<cplx>(), c->stream));
     HIPCHK(hipMemcpyAsync(q.data(), c->matq.ptr, q.size() * sizeof(cplx), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     double g = 0.0;
@@ -2071,8 +2073,10 @@ static int logdet_impl(ldq_ctx *c, const ldq_op *Q, int nparams, const ldq_op *c
     if (k.Q->kind != OPK_LATTICE) return fail(LDQ_E_UNSUPPORTED, "the consistent gradient needs a lattice Q");
     for (int i = 0; i < nparams; ++i) {
       const ldq_op *d = k.dQ[i];
-      if (!(d->kind == OPK_DIAG || (d->kind == OPK_LATTICE && d->lkind == LDQ_SHIFTED_LAPLACIAN)))
-        return fail(LDQ_E_UNSUPPORTED, "the consistent gradient takes diagonal or shifted-Laplacian derivatives");
+      if (!(d->kind == OPK_DIAG || (d->kind == OPK_LATTICE && d->lkind == LDQ_SHIFTED_LAPLACIAN) ||
+            (d->kind == OPK_OBSGRAM && k.Q->ndim == 2 && d->obs9)))
+        return fail(LDQ_E_UNSUPPORTED,
+                    "the consistent gradient takes diagonal, shifted-Laplacian or observation-gram derivatives");
     }
     k.o.probe_block = 0;   // one block: its coefficient history covers every probe
   }

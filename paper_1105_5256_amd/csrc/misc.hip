@@ -428,7 +428,7 @@ template hipError_t launch_mat_accum_shifts<double>(const double *, const cplx *
 // diag (scale * d) or scale * (kd I + L) with Dirichlet L on nx x ny x nz.
 // One workgroup per vector; the workgroup's sum is taken in a fixed order.
 __global__ void lattice_bilinear_kernel(const cplx *z, int nx, int ny, int nz, int diag, double scale, double kd,
-                                        const double *field, cplx *out) {
+                                        const double *field, const double *planes, cplx *out) {
   const int64_t n = (int64_t)nx * ny * nz;
   const cplx *zz = z + (size_t)blockIdx.x * (size_t)n;
   const int dim = nz > 1 ? 3 : 2;
@@ -436,7 +436,22 @@ __global__ void lattice_bilinear_kernel(const cplx *z, int nx, int ny, int nz, i
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
     const cplx zi = zz[i];
     double sr, si;
-    if (diag) {
+    if (planes) {
+      // observation gram A^T A (2-D): plane (dy + 1) 3 + (dx + 1) at site i
+      // holds the entry from i to i + dx + nx dy
+      const int64_t x = i % nx, y = i / nx;
+      double nr = 0.0, ni = 0.0;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (x + dx < 0 || x + dx >= nx || y + dy < 0 || y + dy >= ny) continue;
+          const double w = planes[(size_t)((dy + 1) * 3 + (dx + 1)) * (size_t)n + i];
+          const cplx zo = zz[i + dx + (int64_t)nx * dy];
+          nr += w * zo.re;
+          ni += w * zo.im;
+        }
+      sr = scale * nr;
+      si = scale * ni;
+    } else if (diag) {
       sr = scale * field[i] * zi.re;
       si = scale * field[i] * zi.im;
     } else {
@@ -473,10 +488,10 @@ __global__ void lattice_bilinear_kernel(const cplx *z, int nx, int ny, int nz, i
 }
 
 hipError_t launch_lattice_bilinear(const cplx *z, int nv, int nx, int ny, int nz, bool diag, double scale, double kd,
-                                   const double *field, cplx *out, hipStream_t s) {
+                                   const double *field, const double *planes, cplx *out, hipStream_t s) {
   if (nv <= 0) return hipSuccess;
   hipLaunchKernelGGL(lattice_bilinear_kernel, dim3(nv), dim3(256), 0, s, z, nx, ny, nz, diag ? 1 : 0, scale, kd, field,
-                     out);
+                     planes, out);
   return hipGetLastError();
 }
 }  // namespace ldq

@@ -72,3 +72,31 @@ def test_consistent_gradient_matches_oracle(ctx, shape, kind, k, precision, tol,
     # the diagonal derivative: the probing gradient misses the estimate's derivative by far more
     idiag = 1 if kind == ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN else 0
     assert rel(gp[idiag], G[idiag]) > 1e-4 and rel(gp[idiag], G[idiag]) > 100 * rel(g[idiag], G[idiag])
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(ldq.LDQ_FP64, 1e-11, 1e-7), (ldq.LDQ_MIXED, 1e-6, 1e-3)])
+def test_consistent_gradient_observation_gram(ctx, precision, tol, bound):
+    """The posterior precision Q_p = (kappa2 I + L)^2 + tau A^T A with the
+    derivatives 2 (kappa2 I + L) and the observation gram A^T A."""
+    from paper_1105_5256_amd import workloads
+    shape, k2, tau, k = (26, 22), 0.3, 4.0, 2
+    say(f"consistent gradient, observation gram {shape} precision={precision}")
+    n = int(np.prod(shape))
+    corner, weight = workloads.observations(shape, 120, 3)
+    Q = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SQUARED_SHIFTED_LAPLACIAN, k2))
+    ldq.ldq_op_add_obs(Q, corner, weight, tau)
+    S = ctx.op(ldq.ldq_op_lattice(ctx.handle, shape, ldq.LDQ_SHIFTED_LAPLACIAN, k2, scale=2.0))
+    G = ctx.op(ldq.ldq_op_obs_gram(ctx.handle, Q, corner, weight))
+    M = lattice.shifted_laplacian(shape, k2)
+    Qo = lattice.posterior_precision(lattice.squared(M), corner, weight, tau)
+    dQo = [2 * M, lattice.observation_gram(n, corner, weight)]
+    opts = ldq.ldq_options_default(k=k, tol=tol, grad_tol=tol, precision=precision, consistent_grad=1)
+    v, g, info = ldq.ldq_logdet_grad(ctx.handle, Q, [S, G], opts)
+    C, co = colouring.find_modular(2, 2 * k)
+    col = colouring.modular_colouring(shape, C, co)
+    sig, coef = shifts.log_shifts(info["lambda_min"], info["lambda_max"], 20)
+    Gr, _ = gradient.grad_estimator_rational(Qo, dQo, col, sig, coef)
+    print(f"consistent {g} oracle {Gr} rel {[rel(a, b) for a, b in zip(g, Gr)]}")
+    assert info["ncolours"] == C
+    for a, b in zip(g, Gr):
+        assert rel(a, b) < bound
