@@ -184,7 +184,9 @@ typedef struct {
                                    -sum_j Im sum_l c_l (x^l_j)^T dQ_i x^l_j with x^l_j = (Q - sigma_l I)^{-1}
                                    v_j, from a second Krylov solve that accumulates the shifted
                                    solutions (N complex vectors per probe; lattice Q, derivatives
-                                   diagonal or scaled shifted Laplacians; at most 8192 iterations) */
+                                   diagonal, scaled shifted Laplacians or, on 2-D lattices,
+                                   observation grams; at most 8192 iterations;
+                                   LDQ_E_UNSUPPORTED otherwise) */
 } ldq_options;
 
 /* launch_mode: AUTO and GRAPH capture one chunk of Krylov pass launches into a HIP graph (on a
